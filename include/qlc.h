@@ -1,0 +1,186 @@
+/*
+ * qlc.h -- C ABI of libqlc, an MI355X (gfx950) implementation of Quad Length
+ * Codes (QLC), the lossless code for e4m3 byte streams of arXiv 2602.17849.
+ *
+ * The method (Quad Length Codes and Implementation sections of the paper):
+ *   1. count the 256 byte symbols (histogram);
+ *   2. rank the symbols by decreasing count;
+ *   3. split the ranks into 8 areas named by a 3-bit area code, area a
+ *      holding 2^width[a] ranks (the last one what remains), so a code is
+ *      the area code followed by width[a] suffix bits (Tables 1 and 2);
+ *   4. emit a 256-entry encoder LUT (symbol -> code, length) and a 256-entry
+ *      decoder LUT (rank -> symbol) (Tables 3 and 4);
+ *   5. encode: look up each symbol's code and concatenate the codes;
+ *   6. decode: read 3 bits, which fix the suffix width, read the suffix, add
+ *      the area offset to get the rank, map the rank through the decoder LUT.
+ *
+ * Readings of points the paper leaves open (the stream format):
+ *   - suffix/offset: an area whose width is 8 stores the raw rank as its
+ *     suffix (offset 0); any other area stores rank - first rank of the area
+ *     (reproduces both the decode example, 100|010 -> 34, and the printed
+ *     codes 111_11111101..111_11111111 of ranks 253..255 in Table 3);
+ *   - bit order: each code is written most significant bit first, stream bit
+ *     k is bit (7 - k mod 8) of byte k/8; the stream is zero padded to a
+ *     multiple of 32 bits, so it occupies 4*ceil(total_bits/32) bytes;
+ *   - rank ties: equal counts rank by ascending symbol value; every symbol,
+ *     also one of count 0, gets a code;
+ *   - chunk index: index[j] is the bit offset of symbol j*C; the stream does
+ *     not depend on C (no per-chunk alignment);
+ *   - layout choice: the widths of Table 1 or Table 2, or the cheapest
+ *     non-decreasing width tuple (3639 candidates; 1308 when limited to four
+ *     distinct code lengths), filled greedily in rank order, ties to the
+ *     lexicographically smallest tuple.
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named h_* are host pointers; every other pointer is a DEVICE
+ *     pointer (hipMalloc'd or torch CUDA/ROCm tensor storage).
+ *   - Work is enqueued asynchronously on `stream`; results are valid after
+ *     the stream is synchronised.  The library never allocates or frees on
+ *     these paths; the caller owns every buffer.
+ *   - Argument errors are detected on the host before any launch and are
+ *     returned synchronously (nothing is enqueued).
+ *   - Data-dependent errors (capacity exceeded, corrupt stream) are written
+ *     by the device to *err_out (0 = success, otherwise a qlc_status value;
+ *     the first error found wins).  Outputs are undefined when *err_out != 0.
+ *   - Workspaces: a buffer of at least qlc_workspace_bytes() bytes, zeroed
+ *     once before its first use (qlc_workspace_init or any memset to 0);
+ *     the kernels leave it zeroed-equivalent for the next call.  Calls that
+ *     run concurrently (different streams) need different workspaces.
+ *   - Alignment: `in`, `out`, `bits` and `bits_out` 16 bytes; index and
+ *     total pointers 8 bytes; tables 16 bytes.
+ *   - n < 2^36 symbols per call.
+ */
+#ifndef QLC_H
+#define QLC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QLC_ABI_VERSION 1u
+#define QLC_NUM_SYMBOLS 256
+#define QLC_NUM_AREAS 8
+#define QLC_MAX_CODE_BITS 11
+#define QLC_SERIALIZED_TABLE_BYTES 264
+#define QLC_MIN_CHUNK 256u
+#define QLC_MAX_CHUNK 65536u
+#define QLC_MAX_SYMBOLS_PER_CALL (1ull << 36)
+
+typedef enum qlc_status {
+  QLC_OK = 0,
+  QLC_ERR_INVALID_ARGUMENT = 1,
+  QLC_ERR_CAPACITY = 2,
+  QLC_ERR_CORRUPT_STREAM = 3,
+  QLC_ERR_UNSUPPORTED = 4,
+  QLC_ERR_HIP = 5,
+  QLC_ERR_BUSY = 6
+} qlc_status;
+
+typedef enum qlc_layout_mode {
+  QLC_LAYOUT_SEARCH_QUAD = 0, /* cheapest tuple with <= 4 distinct lengths   */
+  QLC_LAYOUT_SEARCH_ANY = 1,  /* cheapest tuple, any number of lengths       */
+  QLC_LAYOUT_PAPER_T1 = 2,    /* Table 1: widths 3,3,3,3,3,4,5,8             */
+  QLC_LAYOUT_PAPER_T2 = 3     /* Table 2: widths 1,3,3,3,3,5,5,8             */
+} qlc_layout_mode;
+
+/* A complete QLC table (Tables 1-4 in one record).  Plain old data, 1088
+ * bytes, device resident when passed to the codec entry points. */
+typedef struct qlc_table {
+  uint16_t enc[256];        /* encoder LUT by input symbol: (len << 11) | code,
+                               code right aligned, len = 3 + width[area]    */
+  uint8_t rank_to_sym[256]; /* decoder LUT (Table 4)                         */
+  uint8_t sym_to_rank[256]; /* inverse of rank_to_sym                        */
+  uint8_t width[8];         /* suffix bits of each area, non-decreasing      */
+  uint8_t offset[8];        /* rank = offset[a] + suffix                     */
+  uint16_t first[8];        /* first rank of each area                       */
+  uint16_t count[8];        /* ranks held by each area, all >= 1, sum 256    */
+  uint64_t cost_bits;       /* sum of count*length over the histogram used   */
+  uint32_t mode;            /* qlc_layout_mode it was built with             */
+  uint32_t version;         /* QLC_ABI_VERSION                               */
+} qlc_table;
+
+/* Human-readable name of a status. */
+const char* qlc_status_string(qlc_status s);
+
+/* Number of chunk-index entries for n symbols: ceil(n / chunk_symbols). */
+uint64_t qlc_chunk_count(uint64_t n, uint32_t chunk_symbols);
+
+/* Bitstream bytes that suffice for any table: 11 bits per symbol rounded up
+ * to 32-bit words, then to 16 bytes. */
+uint64_t qlc_encode_bound_bytes(uint64_t n);
+
+/* Workspace bytes for a call on n symbols with the given chunk size (the
+ * same workspace serves histogram, table, encode and decode calls). */
+size_t qlc_workspace_bytes(uint64_t n, uint32_t chunk_symbols);
+
+/* Zero a workspace on `stream` (needed once, before its first use). */
+qlc_status qlc_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Step 1 (Observations section): hist_out[s] = number of bytes equal to s,
+ * as 256 uint64 counts. */
+qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Steps 2-4 (Implementation section, Tables 1-4): build *table_out from a
+ * device histogram of 256 uint64 counts. */
+qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
+                                    qlc_table* table_out, hipStream_t stream);
+
+/* Steps 1-4 fused: histogram of `in`, then the table. */
+qlc_status qlc_build_table(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
+                           qlc_table* table_out, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Step 5 (Implementation section, encoding): bits_out receives the
+ * concatenated codes (4*ceil(total/32) bytes, zero padded), chunk_index_out
+ * the ceil(n/C) chunk start offsets, *total_bits_out the stream length in
+ * bits.  chunk_symbols C: a power of two in [256, 65536].  If the stream
+ * would exceed bits_capacity_bytes nothing past the capacity is written and
+ * *err_out = QLC_ERR_CAPACITY. */
+qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
+                      uint32_t chunk_symbols, uint8_t* bits_out,
+                      uint64_t bits_capacity_bytes, uint64_t* chunk_index_out,
+                      uint64_t* total_bits_out, uint32_t* err_out, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Steps 1-5 fused for one tensor: its histogram, a table built from it
+ * with `mode` (written to *table_out), then the encoding as qlc_encode.
+ * Reads the input twice (histogram, then codes) and never re-reads the
+ * table from the host. */
+qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
+                        qlc_table* table_out, uint32_t chunk_symbols,
+                        uint8_t* bits_out, uint64_t bits_capacity_bytes,
+                        uint64_t* chunk_index_out, uint64_t* total_bits_out,
+                        uint32_t* err_out, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Step 6 (Implementation section, decoding): decode n symbols of the stream
+ * `bits` (4*ceil(*total_bits/32) readable bytes) into out.  Each chunk is
+ * decoded independently from its index entry.  *err_out =
+ * QLC_ERR_CORRUPT_STREAM for a suffix outside its area, a chunk that does
+ * not end where the next begins (the last one at *total_bits) or an index
+ * entry out of order. */
+qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits,
+                      const uint64_t* chunk_index, uint32_t chunk_symbols,
+                      const qlc_table* table, uint64_t n, uint8_t* out,
+                      uint32_t* err_out, void* ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+/* Host-side persisted table form: width[8] followed by rank_to_sym[256]. */
+qlc_status qlc_table_serialize(const qlc_table* h_table,
+                               uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]);
+/* Rebuild a full table on the host; rejects widths that are not
+ * non-decreasing in 0..8, that leave an area empty or do not cover 256
+ * ranks, and rank orders that are not a permutation. */
+qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES],
+                                 qlc_table* h_table);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QLC_H */

@@ -1,0 +1,144 @@
+// Device-side building blocks of libqlc (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qlc_internal.h"
+
+namespace qlc {
+
+// ---------------------------------------------------------------------------
+// Candidate width tuples of the layout search (compile-time table).
+// Non-decreasing 8-tuples over 0..8 whose greedy fill leaves every area
+// non-empty (the first seven areas hold fewer than 256 ranks) and covers all
+// 256 ranks, in lexicographic order; widths packed as 4-bit nibbles.
+// ---------------------------------------------------------------------------
+constexpr int kNumCandidates = 3639;
+
+struct CandidateTable {
+  uint32_t packed[kNumCandidates];
+  uint8_t distinct[kNumCandidates];
+  int count;
+};
+
+constexpr CandidateTable make_candidate_table() {
+  CandidateTable t{};
+  int w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int n = 0;
+  while (true) {
+    uint32_t head = 0;
+    for (int a = 0; a < 7; ++a) head += 1u << w[a];
+    if (head < 256 && head + (1u << w[7]) >= 256) {
+      uint32_t pk = 0;
+      int d = 1;
+      for (int a = 0; a < 8; ++a) {
+        pk |= uint32_t(w[a]) << (4 * a);
+        if (a > 0 && w[a] != w[a - 1]) ++d;
+      }
+      if (n < kNumCandidates) {
+        t.packed[n] = pk;
+        t.distinct[n] = uint8_t(d);
+      }
+      ++n;
+    }
+    int pos = 7;
+    while (pos >= 0 && w[pos] == 8) --pos;
+    if (pos < 0) break;
+    ++w[pos];
+    for (int a = pos + 1; a < 8; ++a) w[a] = w[pos];
+  }
+  t.count = n;
+  return t;
+}
+
+// Widths of the two printed schemes (Table 1 and Table 2, "#Symbol bits").
+constexpr uint32_t kPaperT1Packed = 0x85433333u;  // 3,3,3,3,3,4,5,8
+constexpr uint32_t kPaperT2Packed = 0x85533331u;  // 1,3,3,3,3,5,5,8
+
+// ---------------------------------------------------------------------------
+// Wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+  uint32_t lo = __shfl_up((uint32_t)v, d, 64);
+  uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
+  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_inclusive_scan_u64(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t t = shfl_up_u64(v, d);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_u64(v, m);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    uint64_t o = shfl_xor_u64(v, m);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Device-scope atomics on the workspace (visible across the 8 XCD L2s).
+// ---------------------------------------------------------------------------
+// Only relaxed (monotonic) device-scope atomics are used across
+// workgroups: on gfx950 they are coherent loads/stores (sc1) and RMWs,
+// whereas acquire/release fences at device scope write back and invalidate
+// the whole L2 of the XCD.  Cross-workgroup messages therefore carry their
+// own validity tag (a launch epoch) instead of relying on release ordering.
+__device__ __forceinline__ void store_relaxed_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t atomic_add_u32(uint32_t* p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_relaxed_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_relaxed_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// First error wins.  Returns after the CAS has been performed.
+__device__ __forceinline__ void set_error(uint32_t* slot, uint32_t code) {
+  uint32_t expected = 0;
+  __hip_atomic_compare_exchange_strong(slot, &expected, code, __ATOMIC_RELAXED,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+// 32 bits of the concatenation hi:lo starting r bits below the top of hi.
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t r) {
+  return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> (32 - r));
+}
+
+}  // namespace qlc

@@ -1,0 +1,70 @@
+// Internal layout shared by the libqlc host code and kernels (not installed).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qlc.h"
+
+namespace qlc {
+
+// ---- launch geometry ------------------------------------------------------
+constexpr int kHistThreads = 512;     // histogram workgroup
+constexpr int kHistCopies = 32;       // LDS sub-histograms (one per lane mod 32)
+constexpr int kTableThreads = 512;    // table-building workgroup
+constexpr int kEncThreads = 256;      // encode workgroup
+constexpr int kEncSymsPerThread = 16; // one 16-byte load per thread
+constexpr int kEncTile = kEncThreads * kEncSymsPerThread;  // symbols per tile
+constexpr int kDecThreads = 256;      // decode workgroup: one lane per chunk
+constexpr int kDecGroup = 8;          // symbols decoded per window refill
+constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies
+
+// ---- histogram kernel outputs ----------------------------------------------
+constexpr uint32_t kHistSegment = 1;     // write each segment's histogram
+constexpr uint32_t kHistGlobal = 2;      // fold the whole input's histogram
+constexpr uint32_t kHistBuildTable = 4;  // ... and build the table from it
+
+// ---- epoch-tagged cross-workgroup words -----------------------------------
+// [63] valid, [61:40] launch epoch (22 bits), [39:0] value
+constexpr uint32_t kEpochMask = (1u << 22) - 1;
+constexpr uint64_t kValueMask = (1ull << 40) - 1;
+
+// ---- workspace layout -----------------------------------------------------
+struct WsHeader {
+  uint32_t hist_done;   // workgroups finished in the histogram kernel
+  uint32_t enc_ticket;  // next segment handed out by the encode kernel
+  uint32_t enc_done;    // segments finished in the encode kernel
+  uint32_t enc_epoch;   // epoch tag of this encode launch's published words
+  uint32_t enc_err;     // first data error of the encode launch
+  uint32_t dec_done;    // workgroups finished in the decode kernel
+  uint32_t dec_err;     // first data error of the decode launch
+  uint32_t pad[57];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+constexpr size_t kWsHistOffset = 256;                              // u64[8][256]
+constexpr size_t kWsHistBytes = sizeof(uint64_t) * kNumXcd * 256;
+constexpr size_t kWsSegOffset = kWsHistOffset + kWsHistBytes;     // u32[nseg][256], u64[nseg]
+
+// Segments: the unit of the histogram and encode grids, a power of two of
+// at least one encode tile, about 1024 of them for large inputs.
+inline uint32_t seg_log2(uint64_t n) {
+  uint32_t l = 12;                                   // 4096 symbols
+  while (l < 20 && (n >> l) > 1024) ++l;             // ... up to 1 Mi symbols
+  while ((n >> l) > (1ull << 24)) ++l;               // keep the grid bounded
+  return l;
+}
+
+inline uint64_t seg_count(uint64_t n) {
+  const uint32_t l = seg_log2(n);
+  const uint64_t s = (n + (1ull << l) - 1) >> l;
+  return s ? s : 1;
+}
+
+inline size_t ws_bytes_for(uint64_t n) {
+  const uint64_t s = seg_count(n);
+  const size_t b = kWsSegOffset + s * 256 * sizeof(uint32_t) + s * sizeof(uint64_t);
+  return (b + 255) & ~size_t(255);
+}
+
+}  // namespace qlc

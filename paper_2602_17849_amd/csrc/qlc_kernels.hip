@@ -1,0 +1,731 @@
+// libqlc kernels: histogram, table, encode, decode (gfx950, wave64).
+//
+// Paper: Quad Length Codes for Lossless Compression of e4m3 (arXiv
+// 2602.17849).  Section references are to that paper.
+#include <hip/hip_runtime.h>
+
+#include "qlc_device.h"
+#include "qlc_kernels.h"
+
+namespace qlc {
+
+__constant__ CandidateTable g_candidates = make_candidate_table();
+static_assert(make_candidate_table().count == kNumCandidates, "candidate count");
+
+// ===========================================================================
+// Table construction (Implementation section, Tables 1-4).  Run by one
+// workgroup of any size that is a multiple of 64.
+// ===========================================================================
+struct TableSmem {
+  uint64_t h[256];
+  uint64_t P[257];          // P[r] = sum of the counts of ranks < r
+  uint64_t wave_min[16];
+  uint32_t rank[256];       // symbol -> rank
+  uint32_t r2s[256];        // rank -> symbol
+  uint32_t width[8], first[8], count[8], offset[8];
+  uint64_t cost;
+};
+
+__device__ void build_table_block(const uint64_t* h_in, uint32_t mode,
+                                  qlc_table* out, TableSmem& S) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  for (int s = tid; s < 256; s += nt) S.h[s] = h_in[s];
+  __syncthreads();
+
+  // Rank = number of symbols that sort before s: larger count, or equal
+  // count and smaller symbol value.
+  for (int s = tid; s < 256; s += nt) {
+    const uint64_t hs = S.h[s];
+    uint32_t r = 0;
+    for (int u = 0; u < 256; ++u) {
+      const uint64_t hu = S.h[u];
+      r += (hu > hs) | ((hu == hs) & (u < s));
+    }
+    S.rank[s] = r;
+    S.r2s[r] = s;
+  }
+  __syncthreads();
+
+  // Prefix sums of the counts in rank order (wave 0, 4 ranks per lane).
+  if (tid < 64) {
+    const uint64_t v0 = S.h[S.r2s[4 * tid + 0]];
+    const uint64_t v1 = S.h[S.r2s[4 * tid + 1]];
+    const uint64_t v2 = S.h[S.r2s[4 * tid + 2]];
+    const uint64_t v3 = S.h[S.r2s[4 * tid + 3]];
+    const uint64_t local = v0 + v1 + v2 + v3;
+    const uint64_t incl = wave_inclusive_scan_u64(local);
+    const uint64_t excl = incl - local;
+    S.P[4 * tid + 0] = excl;
+    S.P[4 * tid + 1] = excl + v0;
+    S.P[4 * tid + 2] = excl + v0 + v1;
+    S.P[4 * tid + 3] = excl + v0 + v1 + v2;
+    if (tid == 63) S.P[256] = incl;
+  }
+  __syncthreads();
+
+  // Layout: fixed printed widths, or the cheapest candidate (ties to the
+  // smallest index = lexicographically smallest tuple).
+  uint32_t packed;
+  if (mode == QLC_LAYOUT_PAPER_T1) {
+    packed = kPaperT1Packed;
+  } else if (mode == QLC_LAYOUT_PAPER_T2) {
+    packed = kPaperT2Packed;
+  } else {
+    const uint32_t max_distinct = (mode == QLC_LAYOUT_SEARCH_QUAD) ? 4u : 8u;
+    uint64_t best = ~0ull;
+    for (int c = tid; c < kNumCandidates; c += nt) {
+      if (g_candidates.distinct[c] > max_distinct) continue;
+      const uint32_t pk = g_candidates.packed[c];
+      uint32_t f = 0;
+      uint64_t cost = 0;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const uint32_t b = (pk >> (4 * a)) & 15u;
+        const uint32_t cap = 1u << b;
+        const uint32_t cnt = cap < 256u - f ? cap : 256u - f;
+        cost += (uint64_t)(3 + b) * (S.P[f + cnt] - S.P[f]);
+        f += cnt;
+      }
+      const uint64_t key = (cost << 12) | (uint64_t)c;
+      best = key < best ? key : best;
+    }
+    best = wave_min_u64(best);
+    if ((tid & 63) == 0) S.wave_min[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t m = S.wave_min[0];
+      for (int w = 1; w < nt / 64; ++w) m = S.wave_min[w] < m ? S.wave_min[w] : m;
+      S.wave_min[0] = m;
+    }
+    __syncthreads();
+    packed = g_candidates.packed[S.wave_min[0] & 0xFFF];
+  }
+
+  // Greedy fill, offsets (an 8-bit area carries the raw rank), cost.
+  if (tid == 0) {
+    uint32_t f = 0;
+    uint64_t cost = 0;
+    for (int a = 0; a < 8; ++a) {
+      const uint32_t b = (packed >> (4 * a)) & 15u;
+      const uint32_t cap = 1u << b;
+      const uint32_t cnt = cap < 256u - f ? cap : 256u - f;
+      S.width[a] = b;
+      S.first[a] = f;
+      S.count[a] = cnt;
+      S.offset[a] = (b == 8) ? 0u : f;
+      cost += (uint64_t)(3 + b) * (S.P[f + cnt] - S.P[f]);
+      f += cnt;
+    }
+    S.cost = cost;
+  }
+  __syncthreads();
+
+  // Encoder LUT (Table 3), indexed by input symbol.
+  for (int s = tid; s < 256; s += nt) {
+    const uint32_t r = S.rank[s];
+    uint32_t a = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) a = (r >= S.first[k]) ? (uint32_t)k : a;
+    const uint32_t b = S.width[a];
+    const uint32_t code = (a << b) | (r - S.offset[a]);
+    out->enc[s] = (uint16_t)(((3 + b) << 11) | code);
+    out->rank_to_sym[s] = (uint8_t)S.r2s[s];
+    out->sym_to_rank[s] = (uint8_t)r;
+  }
+  if (tid < 8) {
+    out->width[tid] = (uint8_t)S.width[tid];
+    out->offset[tid] = (uint8_t)S.offset[tid];
+    out->first[tid] = (uint16_t)S.first[tid];
+    out->count[tid] = (uint16_t)S.count[tid];
+  }
+  if (tid == 0) {
+    out->cost_bits = S.cost;
+    out->mode = mode;
+    out->version = QLC_ABI_VERSION;
+  }
+}
+
+__global__ __launch_bounds__(kTableThreads) void k_table_from_hist(
+    const uint64_t* __restrict__ hist, uint32_t mode, qlc_table* __restrict__ out) {
+  __shared__ TableSmem S;
+  build_table_block(hist, mode, out, S);
+}
+
+// ===========================================================================
+// Histogram (Observations section: the PMF of the 256 byte symbols).
+//
+// One workgroup per segment of 2^log2_seg symbols.  The workgroup keeps 32
+// LDS copies of the histogram, one per lane mod 32, so the lanes of a wave
+// never collide on a bin even under extreme skew.  Outputs, each optional:
+//   - the segment's own histogram (uint32[256]), which the encoder turns
+//     into the segment's bit count once the table is known;
+//   - the whole input's histogram, accumulated with device-scope atomics
+//     into per-XCD uint64 partials and folded by the last workgroup, which
+//     can then build the table in place.
+// ===========================================================================
+union HistSmem {
+  uint32_t sub[256 * kHistCopies];
+  TableSmem table;
+};
+
+__device__ __forceinline__ void hist_add_word(uint32_t* sub, uint32_t w, uint32_t copy) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t b = (w >> (8 * k)) & 0xFFu;
+    atomicAdd(&sub[(b << 5) | copy], 1u);
+  }
+}
+
+__device__ __forceinline__ void hist_add_vec(uint32_t* sub, uint4 v, uint32_t copy) {
+  hist_add_word(sub, v.x, copy);
+  hist_add_word(sub, v.y, copy);
+  hist_add_word(sub, v.z, copy);
+  hist_add_word(sub, v.w, copy);
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_histogram(
+    const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg, WsHeader* __restrict__ hdr,
+    uint64_t* __restrict__ xcd_part, uint32_t* __restrict__ seg_hist,
+    uint64_t* __restrict__ hist_out, uint32_t flags, uint32_t mode,
+    qlc_table* __restrict__ table_out) {
+  __shared__ HistSmem S;
+  __shared__ uint32_t is_last;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < 256 * kHistCopies; i += kHistThreads) S.sub[i] = 0;
+  __syncthreads();
+
+  const uint32_t copy = tid & (kHistCopies - 1);
+  const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
+  const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
+  const uint4* vin = reinterpret_cast<const uint4*>(in);
+  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
+  uint64_t i = v0 + tid;
+  for (; i + 3 * kHistThreads < v1; i += 4 * kHistThreads) {
+    const uint4 a = vin[i];
+    const uint4 b = vin[i + kHistThreads];
+    const uint4 c = vin[i + 2 * kHistThreads];
+    const uint4 d = vin[i + 3 * kHistThreads];
+    hist_add_vec(S.sub, a, copy);
+    hist_add_vec(S.sub, b, copy);
+    hist_add_vec(S.sub, c, copy);
+    hist_add_vec(S.sub, d, copy);
+  }
+  for (; i < v1; i += kHistThreads) hist_add_vec(S.sub, vin[i], copy);
+  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += kHistThreads)  // ragged tail of the input
+    atomicAdd(&S.sub[((uint32_t)in[j] << 5) | copy], 1u);
+  __syncthreads();
+
+  if (tid < 256) {
+    uint32_t s = 0;
+#pragma unroll 8
+    for (uint32_t c = 0; c < kHistCopies; ++c) s += S.sub[(tid << 5) | ((c + tid) & 31)];
+    if (flags & kHistSegment) seg_hist[(uint64_t)blockIdx.x * 256 + tid] = s;
+    if ((flags & kHistGlobal) && s)
+      atomicAdd((unsigned long long*)&xcd_part[(blockIdx.x % kNumXcd) * 256 + tid],
+                (unsigned long long)s);
+  }
+  if (!(flags & kHistGlobal)) return;
+  // Every partial must be performed before this workgroup counts as done:
+  // wait for the atomics to be acknowledged (device-scope atomics are
+  // coherent across XCDs, so no cache flush is needed).
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) is_last = (atomic_add_u32(&hdr->hist_done, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (!is_last) return;
+
+  uint64_t* hsum = S.table.h;  // reuse LDS (sub is no longer needed)
+  if (tid < 256) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int x = 0; x < kNumXcd; ++x) s += load_relaxed_u64(&xcd_part[x * 256 + tid]);
+    if (hist_out) hist_out[tid] = s;
+    hsum[tid] = s;
+#pragma unroll
+    for (int x = 0; x < kNumXcd; ++x) store_relaxed_u64(&xcd_part[x * 256 + tid], 0);
+  }
+  if (tid == 0) store_relaxed_u32(&hdr->hist_done, 0);
+  __syncthreads();
+  if (flags & kHistBuildTable) build_table_block(hsum, mode, table_out, S.table);
+}
+
+// ===========================================================================
+// Encode (Implementation section: look up each code, concatenate).
+//
+// One workgroup per segment (the histogram kernel's segments), segments
+// numbered by an atomic ticket.  A segment's bit count is the dot product
+// of its histogram with the code lengths, so every workgroup publishes its
+// count at once and sums its predecessors' counts (all published within a
+// few microseconds: no serial look-back chain).  The workgroup then walks
+// its segment in tiles of 4096 symbols: LUT gather from LDS, block scan of
+// the code lengths, bit packing into LDS at the running global alignment,
+// coalesced stores of the whole words; the partial last word is carried
+// into the next tile.  A segment's first word also holds the last bits of
+// the previous segment, which the workgroup recomputes from the 16 input
+// bytes before its segment; its own partial last word is left to the next
+// segment (the last segment pads and stores it).
+// ===========================================================================
+struct EncSmem {
+  uint16_t lut[256];
+  uint32_t words[kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
+  uint64_t red[kEncThreads / 64];
+  uint32_t wave_sum[kEncThreads / 64];
+  uint32_t seg, epoch, cap_hit;
+  uint64_t prefix;
+};
+
+__device__ __forceinline__ uint32_t clamp_len(uint32_t e) {
+  const uint32_t l = e >> 11;  // <= 11 in any valid table; the clamp guards LDS bounds
+  return l < QLC_MAX_CODE_BITS ? l : QLC_MAX_CODE_BITS;
+}
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
+  v = wave_sum_u64(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kEncThreads / 64; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kEncThreads) void k_encode(
+    const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
+    const qlc_table* __restrict__ table, const uint32_t* __restrict__ seg_hist,
+    uint32_t log2_chunk, uint32_t* __restrict__ bits_out, uint64_t cap_words,
+    uint64_t* __restrict__ index_out, uint64_t* __restrict__ total_out,
+    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr, uint64_t* __restrict__ seg_word,
+    uint32_t nseg) {
+  __shared__ EncSmem S;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    S.seg = atomic_add_u32(&hdr->enc_ticket, 1u);
+    S.epoch = load_relaxed_u32(&hdr->enc_epoch) & kEpochMask;
+    S.cap_hit = 0;
+  }
+  const uint32_t e_t = table->enc[tid];
+  S.lut[tid] = (uint16_t)e_t;
+  __syncthreads();
+  const uint32_t seg = S.seg;
+  const uint32_t epoch = S.epoch;
+  const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
+
+  // ---- this segment's bit count, published; the predecessors' summed ----
+  const uint64_t my_bits =
+      block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * clamp_len(e_t), S.red);
+  if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | my_bits);
+  uint64_t pre = 0;
+  for (uint32_t k = tid; k < seg; k += kEncThreads) {
+    uint64_t w;
+    do {
+      w = load_relaxed_u64(&seg_word[k]);
+    } while ((w & ~kValueMask) != tag);
+    pre += w & kValueMask;
+  }
+  const uint64_t G = block_sum_u64(pre, S.red);
+  if (seg == nseg - 1 && tid == 0) *total_out = G + my_bits;
+
+  // ---- last bits of the previous segment (recomputed from its input) ----
+  const uint64_t seg0 = (uint64_t)seg << log2_seg;
+  uint32_t carry = 0;  // bits [G & ~31, G) of the stream, MSB aligned
+  if ((G & 31) != 0) {
+    uint64_t acc = 0;
+    for (int k = 16; k >= 1; --k) {
+      const uint32_t e = S.lut[in[seg0 - k]];
+      acc = (acc << clamp_len(e)) | (e & 0x7FFu);
+    }
+    const uint32_t g = (uint32_t)(G & 31);
+    carry = ((uint32_t)acc) << (32 - g);
+  }
+
+  // ---- tiles of 4096 symbols ----
+  const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
+  const bool last_seg = (seg == nseg - 1);
+  uint64_t R = G;  // global bit offset of the current tile
+  bool cap = false;
+  for (uint64_t t0 = seg0; t0 < seg1 || (t0 == seg0 && seg1 == seg0); t0 += kEncTile) {
+    const uint64_t base = t0 + (uint64_t)tid * kEncSymsPerThread;
+    uint32_t sw[4] = {0, 0, 0, 0};
+    uint32_t nv = 0;
+    if (base + kEncSymsPerThread <= seg1) {
+      const uint4 v = *reinterpret_cast<const uint4*>(in + base);
+      sw[0] = v.x; sw[1] = v.y; sw[2] = v.z; sw[3] = v.w;
+      nv = kEncSymsPerThread;
+    } else if (base < seg1) {
+      nv = (uint32_t)(seg1 - base);
+      for (uint32_t k = 0; k < nv; ++k) sw[k >> 2] |= (uint32_t)in[base + k] << (8 * (k & 3));
+    }
+    uint32_t code[kEncSymsPerThread], len[kEncSymsPerThread];
+    uint32_t mybits = 0;
+#pragma unroll
+    for (int k = 0; k < kEncSymsPerThread; ++k) {
+      const uint32_t e = S.lut[(sw[k >> 2] >> (8 * (k & 3))) & 0xFFu];
+      const bool valid = (uint32_t)k < nv;
+      len[k] = valid ? clamp_len(e) : 0u;
+      code[k] = valid ? (e & 0x7FFu) : 0u;
+      mybits += len[k];
+    }
+    // block exclusive scan of the per-thread bit counts
+    const uint32_t incl = wave_inclusive_scan_u32(mybits);
+    if (lane == 63) S.wave_sum[wave] = incl;
+    const uint32_t g = (uint32_t)(R & 31);
+    // zero the tile's word buffer, word 0 starts with the carried bits
+    for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) S.words[w] = w ? 0u : carry;
+    __syncthreads();
+    uint32_t wave_off = 0, tile_bits = 0;
+#pragma unroll
+    for (int w = 0; w < kEncThreads / 64; ++w) {
+      const uint32_t ws = S.wave_sum[w];
+      wave_off += (w < (int)wave) ? ws : 0u;
+      tile_bits += ws;
+    }
+    const uint32_t off = wave_off + incl - mybits;
+    // pack this thread's codes at bit g + off of the tile buffer, MSB first
+    {
+      uint64_t acc = 0;
+      uint32_t nacc = (g + off) & 31u;
+      uint32_t widx = (g + off) >> 5;
+#pragma unroll
+      for (int k = 0; k < kEncSymsPerThread; ++k) {
+        acc = (acc << len[k]) | code[k];
+        nacc += len[k];
+        if (nacc >= 32) {
+          nacc -= 32;
+          atomicOr(&S.words[widx], (uint32_t)(acc >> nacc));
+          ++widx;
+        }
+      }
+      if (nacc) atomicOr(&S.words[widx], (uint32_t)(acc << (32 - nacc)));
+    }
+    if (base < seg1 && (base & ((1ull << log2_chunk) - 1)) == 0)
+      index_out[base >> log2_chunk] = R + off;
+    __syncthreads();
+    // store the whole words (and, at the very end, the padded last word)
+    const uint32_t endb = g + tile_bits;
+    const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
+    const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
+    const uint64_t w0 = R >> 5;
+    for (uint32_t i = tid; i < nw; i += kEncThreads) {
+      if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
+      else cap = true;
+    }
+    carry = S.words[endb >> 5];  // partial last word (garbage-free: zero padded)
+    R += tile_bits;
+    __syncthreads();
+    if (seg1 == seg0) break;  // empty input: one pass with no symbols
+  }
+  if (cap) S.cap_hit = 1;
+  __syncthreads();
+
+  // ---- last workgroup to finish publishes the error and resets the state ----
+  if (tid == 0) {
+    if (S.cap_hit) set_error(&hdr->enc_err, QLC_ERR_CAPACITY);
+    const uint32_t done = atomic_add_u32(&hdr->enc_done, 1u);
+    if (done == nseg - 1) {
+      *err_out = load_relaxed_u32(&hdr->enc_err);
+      store_relaxed_u32(&hdr->enc_err, 0);
+      store_relaxed_u32(&hdr->enc_ticket, 0);
+      store_relaxed_u32(&hdr->enc_done, 0);
+      store_relaxed_u32(&hdr->enc_epoch, (epoch + 1) & kEpochMask);
+    }
+  }
+}
+
+// ===========================================================================
+// Decode (Implementation section: 3 bits give the area and thus the suffix
+// width; suffix + offset = rank; rank -> symbol via the decoder LUT).
+//
+// One lane per chunk.  The decoder LUT is re-indexed by the whole code
+// word: because widths never decrease, the codes of area a occupy the
+// integer range [a << w_a, (a + 1) << w_a) and these ranges are disjoint,
+// so a 2048-entry LDS table maps code -> symbol (bit 15 flags an invalid
+// suffix).  The per-symbol chain is pure VALU: the 3-bit area code selects
+// the shift 29 - w_a from an 8-byte register table (v_perm), the code is
+// the window shifted right by it, and three funnel shifts advance a 96-bit
+// window by 3 + w_a bits.
+//
+// Each lane streams its chunk through a private 8-block LDS ring (16-byte
+// blocks, plus a mirror of block 0 so a 4-word window never wraps).  Blocks
+// are fetched with bounds-checked buffer loads, at most one per 8-symbol
+// group, and written into the ring two groups after their load was issued
+// (two alternating register buffers), so the load latency hides behind two
+// groups of decoding of every wave on the SIMD.  Lanes that need no block
+// still issue the load with an out-of-range offset (returns zeros, touches
+// no memory) so that every wave waits at a fixed program point.
+// ===========================================================================
+constexpr int kRingStride = 36;          // 32 ring words + 4 mirror words (144 B)
+constexpr uint32_t kLookaheadBits = 512;
+constexpr uint32_t kOobOffset = 0xFFFFFFF0u;
+constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
+
+struct DecSmem {
+  uint16_t lut[2048];
+  uint32_t ring[kDecThreads * kRingStride];
+};
+
+__device__ __forceinline__ uint4 load_block(__amdgpu_buffer_rsrc_t rsrc, uint32_t off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
+  return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ void ring_put(uint32_t* ring, uint64_t blk, uint4 v) {
+  const uint32_t slot = (uint32_t)(blk & 7u) * 4u;
+  const uint4 w = make_uint4(__builtin_bswap32(v.x), __builtin_bswap32(v.y),
+                             __builtin_bswap32(v.z), __builtin_bswap32(v.w));
+  *reinterpret_cast<uint4*>(ring + slot) = w;
+  if (slot == 0) *reinterpret_cast<uint4*>(ring + 32) = w;
+}
+
+struct DecLane {
+  uint32_t* ring;
+  uint64_t pm1;        // bit position of the next symbol, minus one
+  uint32_t sh_lo, sh_hi;
+  uint32_t errbits;
+};
+
+// Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
+__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
+  const uint32_t q = (uint32_t)L.pm1;
+  const uint32_t wi = (q >> 5) & 31u;
+  const uint32_t w0 = L.ring[wi], w1 = L.ring[wi + 1], w2 = L.ring[wi + 2], w3 = L.ring[wi + 3];
+  const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - ((pos) & 31), or 0
+  uint32_t A = __builtin_amdgcn_alignbit(w0, w1, sh0);
+  uint32_t B = __builtin_amdgcn_alignbit(w1, w2, sh0);
+  uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, sh0);
+  uint32_t e[8];
+  uint32_t ssum = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
+    const uint32_t s = __builtin_amdgcn_perm(L.sh_hi, L.sh_lo, sel);  // 29 - width
+    e[k] = lut[A >> s];
+    A = __builtin_amdgcn_alignbit(A, B, s);
+    B = __builtin_amdgcn_alignbit(B, Cw, s);
+    Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
+    ssum += s;
+  }
+  L.pm1 += 256u - ssum;  // 8 codes of 32 - s bits each
+  uint2 r;
+  r.x = __builtin_amdgcn_perm(e[1], e[0], 0x0C0C0400u) | __builtin_amdgcn_perm(e[3], e[2], 0x04000C0Cu);
+  r.y = __builtin_amdgcn_perm(e[5], e[4], 0x0C0C0400u) | __builtin_amdgcn_perm(e[7], e[6], 0x04000C0Cu);
+  L.errbits |= e[0] | e[1] | e[2] | e[3] | e[4] | e[5] | e[6] | e[7];
+  return r;
+}
+
+__global__ __launch_bounds__(kDecThreads) void k_decode(
+    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
+    const uint64_t* __restrict__ index, uint32_t log2_chunk,
+    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out,
+    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
+  __shared__ DecSmem S;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t total = *total_p;
+
+  // ---- code -> symbol LUT and the per-area shift table ----
+  uint32_t sh_lo = 0, sh_hi = 0;  // byte a = 29 - width[a]
+  {
+    uint32_t w[8], lo[8], off[8], first[8], cnt[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      w[a] = table->width[a] < 8 ? table->width[a] : 8u;  // keeps codes < 2048
+      off[a] = table->offset[a];
+      first[a] = table->first[a];
+      cnt[a] = table->count[a];
+      lo[a] = (uint32_t)a << w[a];
+      if (a < 4) sh_lo |= (29u - w[a]) << (8 * a);
+      else sh_hi |= (29u - w[a]) << (8 * (a - 4));
+    }
+    for (uint32_t c = tid; c < 2048; c += kDecThreads) {
+      uint16_t e = 0x8000;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        if (c >= lo[a] && c < lo[a] + (1u << w[a])) {
+          const uint32_t rank = off[a] + (c - lo[a]);
+          if (rank >= first[a] && rank < first[a] + cnt[a] && rank < 256)
+            e = table->rank_to_sym[rank];
+        }
+      }
+      S.lut[c] = e;
+    }
+  }
+  __syncthreads();
+
+  const uint32_t C = 1u << log2_chunk;
+  const uint64_t nchunks = (n + C - 1) >> log2_chunk;
+  const uint64_t j = (uint64_t)blockIdx.x * kDecThreads + tid;
+  const uint64_t j_wave = (uint64_t)blockIdx.x * kDecThreads +
+                          (uint64_t)(__builtin_amdgcn_readfirstlane(tid) & ~63u);
+  bool bad = false;
+
+  if (j_wave < nchunks) {
+    // Buffer resource rebased at the wave's first chunk: loads past the end
+    // of the stream (or through a corrupt index) return zeros.
+    const uint64_t stream_bytes = ((total + 31) >> 5) << 2;
+    const uint64_t wave_bit = index[j_wave];
+    const uint64_t base_blk =
+        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 7)) |
+        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 39)) << 32);
+    const uint64_t base_byte = base_blk << 4;
+    uint64_t avail = stream_bytes > base_byte ? stream_bytes - base_byte : 0;
+    if (avail > kOobOffset) avail = kOobOffset;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(bits + (base_byte < stream_bytes ? base_byte : 0)), (short)0,
+        (int)(uint32_t)avail, 0x00020000);
+
+    if (j < nchunks) {
+      const uint64_t pos0 = index[j];
+      const uint64_t end = (j + 1 < nchunks) ? index[j + 1] : total;
+      const uint64_t left = n - (j << log2_chunk);
+      const uint32_t nsym = (uint32_t)(left < C ? left : C);
+      if (pos0 > end || end > total || (j == 0 && pos0 != 0) || pos0 < wave_bit ||
+          ((pos0 >> 7) - base_blk) > (kOobOffset >> 4) - 64) {
+        bad = true;
+      } else {
+        DecLane L;
+        L.ring = S.ring + tid * kRingStride;
+        L.pm1 = pos0 - 1;
+        L.sh_lo = sh_lo;
+        L.sh_hi = sh_hi;
+        L.errbits = 0;
+        uint32_t fb = (uint32_t)((pos0 >> 7) - base_blk);  // next block to fetch (wave-relative)
+        const uint32_t bb0 = (uint32_t)base_blk;  // ring slots follow absolute block numbers
+        {
+          uint4 pre[5];
+#pragma unroll
+          for (int b = 0; b < 5; ++b) pre[b] = load_block(rsrc, (fb + b) << 4);
+#pragma unroll
+          for (int b = 0; b < 5; ++b) ring_put(L.ring, bb0 + fb + b, pre[b]);
+        }
+        fb += 5;
+        // wave-relative bit position of the next symbol, for the refill test
+        const uint64_t rel0 = base_blk << 7;
+        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa;
+        uint32_t ba = 0, bb = 0;
+        bool va = false, vb = false;
+        uint8_t* o = out + (j << log2_chunk);
+        const uint32_t groups = nsym >> 3;
+        uint32_t g = 0;
+        for (; g + 2 <= groups; g += 2) {
+          *reinterpret_cast<uint2*>(o + g * 8) = decode_group(L, S.lut);
+          if (va) ring_put(L.ring, bb0 + ba, pa);
+          va = ((uint64_t)fb << 7) < (L.pm1 + 1 - rel0) + kLookaheadBits;
+          ba = fb;
+          pa = load_block(rsrc, va ? (fb << 4) : kOobOffset);
+          fb += va ? 1u : 0u;
+          *reinterpret_cast<uint2*>(o + g * 8 + 8) = decode_group(L, S.lut);
+          if (vb) ring_put(L.ring, bb0 + bb, pb);
+          vb = ((uint64_t)fb << 7) < (L.pm1 + 1 - rel0) + kLookaheadBits;
+          bb = fb;
+          pb = load_block(rsrc, vb ? (fb << 4) : kOobOffset);
+          fb += vb ? 1u : 0u;
+        }
+        if (va) ring_put(L.ring, bb0 + ba, pa);
+        if (vb) ring_put(L.ring, bb0 + bb, pb);
+        if (g < groups) {  // odd number of groups (last chunk only)
+          *reinterpret_cast<uint2*>(o + g * 8) = decode_group(L, S.lut);
+          ++g;
+        }
+        const uint32_t rem = nsym - groups * 8;
+        if (rem) {  // final partial group of the last chunk
+          const uint32_t q = (uint32_t)L.pm1;
+          const uint32_t wi = (q >> 5) & 31u;
+          uint32_t A = __builtin_amdgcn_alignbit(L.ring[wi], L.ring[wi + 1], ~q);
+          uint32_t B = __builtin_amdgcn_alignbit(L.ring[wi + 1], L.ring[wi + 2], ~q);
+          uint32_t Cw = __builtin_amdgcn_alignbit(L.ring[wi + 2], L.ring[wi + 3], ~q);
+          for (uint32_t k = 0; k < rem; ++k) {
+            const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
+            const uint32_t s = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
+            const uint32_t e = S.lut[A >> s];
+            L.errbits |= e;
+            o[groups * 8 + k] = (uint8_t)e;
+            A = __builtin_amdgcn_alignbit(A, B, s);
+            B = __builtin_amdgcn_alignbit(B, Cw, s);
+            Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
+            L.pm1 += 32u - s;
+          }
+        }
+        bad = (L.errbits & 0x8000u) || (L.pm1 + 1 != end);
+      }
+    }
+  }
+
+  // ---- error word: first error wins; the last workgroup publishes it ----
+  if (bad) set_error(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM);
+  __syncthreads();
+  if (tid == 0) {
+    const uint32_t done = atomic_add_u32(&hdr->dec_done, 1u);
+    if (done == gridDim.x - 1) {
+      *err_out = load_relaxed_u32(&hdr->dec_err);
+      store_relaxed_u32(&hdr->dec_err, 0);
+      store_relaxed_u32(&hdr->dec_done, 0);
+    }
+  }
+}
+
+// ===========================================================================
+// Workspace zeroing (a fill kernel, so that callers may capture it).
+// ===========================================================================
+__global__ void k_zero_words(uint32_t* __restrict__ p, uint64_t nwords) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace qlc
+
+// ===========================================================================
+// Host-side launchers
+// ===========================================================================
+namespace qlc {
+
+hipError_t launch_histogram(const uint8_t* in, uint64_t n, WsHeader* hdr, uint64_t* xcd_part,
+                            uint32_t* seg_hist, uint64_t* hist_out, uint32_t flags, uint32_t mode,
+                            qlc_table* table_out, hipStream_t stream) {
+  const uint32_t l = seg_log2(n);
+  hipLaunchKernelGGL(k_histogram, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), 0, stream, in,
+                     n, l, hdr, xcd_part, seg_hist, hist_out, flags, mode, table_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_from_hist(const uint64_t* hist, uint32_t mode, qlc_table* out,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(k_table_from_hist, dim3(1), dim3(kTableThreads), 0, stream, hist, mode, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
+                         const uint32_t* seg_hist, uint32_t log2_chunk, uint32_t* bits_out,
+                         uint64_t cap_words, uint64_t* index_out, uint64_t* total_out,
+                         uint32_t* err_out, WsHeader* hdr, uint64_t* seg_word, hipStream_t stream) {
+  const uint32_t nseg = (uint32_t)seg_count(n);
+  hipLaunchKernelGGL(k_encode, dim3(nseg), dim3(kEncThreads), 0, stream, in, n, seg_log2(n), table,
+                     seg_hist, log2_chunk, bits_out, cap_words, index_out, total_out, err_out, hdr,
+                     seg_word, nseg);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint64_t* index,
+                         uint32_t log2_chunk, const qlc_table* table, uint64_t n, uint8_t* out,
+                         uint32_t* err_out, WsHeader* hdr, hipStream_t stream) {
+  const uint64_t nchunks = (n + (1ull << log2_chunk) - 1) >> log2_chunk;
+  uint64_t blocks = (nchunks + kDecThreads - 1) / kDecThreads;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_decode, dim3((uint32_t)blocks), dim3(kDecThreads), 0, stream, bits, total,
+                     index, log2_chunk, table, n, out, err_out, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t stream) {
+  const uint64_t nwords = bytes / 4;
+  uint64_t blocks = (nwords + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_zero_words, dim3((uint32_t)blocks), dim3(256), 0, stream,
+                     static_cast<uint32_t*>(p), nwords);
+  return hipGetLastError();
+}
+
+}  // namespace qlc

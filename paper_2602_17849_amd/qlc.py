@@ -1,0 +1,270 @@
+"""Python binding of libqlc (argument marshalling only).
+
+Every function named ``qlc_*`` mirrors the C entry point of the same name in
+include/qlc.h: torch tensors provide device memory (``data_ptr()``) and the
+current torch stream provides the HIP stream; all work runs in the HIP
+kernels of libqlc.so.  There is no fallback: if the library is missing the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqlc.so")
+
+QLC_OK = 0
+QLC_ERR_INVALID_ARGUMENT = 1
+QLC_ERR_CAPACITY = 2
+QLC_ERR_CORRUPT_STREAM = 3
+QLC_ERR_UNSUPPORTED = 4
+QLC_ERR_HIP = 5
+QLC_ERR_BUSY = 6
+
+LAYOUT_SEARCH_QUAD = 0
+LAYOUT_SEARCH_ANY = 1
+LAYOUT_PAPER_T1 = 2
+LAYOUT_PAPER_T2 = 3
+
+TABLE_BYTES = 1088
+SERIALIZED_TABLE_BYTES = 264
+MIN_CHUNK = 256
+MAX_CHUNK = 65536
+
+
+class QLCError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, _status_string(status), status))
+
+
+class _Table(ctypes.Structure):
+    _fields_ = [
+        ("enc", ctypes.c_uint16 * 256),
+        ("rank_to_sym", ctypes.c_uint8 * 256),
+        ("sym_to_rank", ctypes.c_uint8 * 256),
+        ("width", ctypes.c_uint8 * 8),
+        ("offset", ctypes.c_uint8 * 8),
+        ("first", ctypes.c_uint16 * 8),
+        ("count", ctypes.c_uint16 * 8),
+        ("cost_bits", ctypes.c_uint64),
+        ("mode", ctypes.c_uint32),
+        ("version", ctypes.c_uint32),
+    ]
+
+
+assert ctypes.sizeof(_Table) == TABLE_BYTES
+
+_lib = None
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+
+_SIGNATURES = {
+    "qlc_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "qlc_chunk_count": ([_u64, _u32], _u64),
+    "qlc_encode_bound_bytes": ([_u64], _u64),
+    "qlc_workspace_bytes": ([_u64, _u32], _sz),
+    "qlc_workspace_init": ([_vp, _sz, _vp], ctypes.c_int),
+    "qlc_histogram": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_table_from_histogram": ([_vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
+    "qlc_build_table": ([_vp, _u64, ctypes.c_int, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_encode": ([_vp, _u64, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_compress": ([_vp, _u64, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp],
+                     ctypes.c_int),
+    "qlc_decode": ([_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_table_serialize": ([_vp, _vp], ctypes.c_int),
+    "qlc_table_deserialize": ([_vp, _vp], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libqlc.so (built in-tree by paper_2602_17849_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libqlc.so is not built; run `python -m paper_2602_17849_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _status_string(s: int) -> str:
+    try:
+        return lib().qlc_status_string(int(s)).decode()
+    except Exception:  # the library could not be loaded
+        return "status %d" % s
+
+
+def _check(st: int, what: str):
+    if st != QLC_OK:
+        raise QLCError(st, what)
+
+
+def _p(t) -> int:
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
+
+
+# ------------------------------------------------------------ size queries
+def qlc_chunk_count(n: int, chunk_symbols: int) -> int:
+    return int(lib().qlc_chunk_count(n, chunk_symbols))
+
+
+def qlc_encode_bound_bytes(n: int) -> int:
+    return int(lib().qlc_encode_bound_bytes(n))
+
+
+def qlc_workspace_bytes(n: int, chunk_symbols: int = 4096) -> int:
+    return int(lib().qlc_workspace_bytes(n, chunk_symbols))
+
+
+# ------------------------------------------------------------ entry points
+def qlc_workspace_init(ws: torch.Tensor, stream=None):
+    _check(lib().qlc_workspace_init(_p(ws), _nbytes(ws), _stream(stream)), "qlc_workspace_init")
+
+
+def qlc_histogram(x: torch.Tensor, hist_out: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_histogram(_p(x), x.numel(), _p(hist_out), _p(ws), _nbytes(ws),
+                               _stream(stream)), "qlc_histogram")
+
+
+def qlc_table_from_histogram(hist: torch.Tensor, mode: int, table_out: torch.Tensor, stream=None):
+    _check(lib().qlc_table_from_histogram(_p(hist), mode, _p(table_out), _stream(stream)),
+           "qlc_table_from_histogram")
+
+
+def qlc_build_table(x: torch.Tensor, mode: int, table_out: torch.Tensor, ws: torch.Tensor,
+                    stream=None):
+    _check(lib().qlc_build_table(_p(x), x.numel(), mode, _p(table_out), _p(ws), _nbytes(ws),
+                                 _stream(stream)), "qlc_build_table")
+
+
+def qlc_encode(x: torch.Tensor, table: torch.Tensor, chunk_symbols: int, bits_out: torch.Tensor,
+               index_out: torch.Tensor, total_out: torch.Tensor, err_out: torch.Tensor,
+               ws: torch.Tensor, stream=None, n: int | None = None):
+    n = x.numel() if n is None else n
+    _check(lib().qlc_encode(_p(x), n, _p(table), chunk_symbols, _p(bits_out), _nbytes(bits_out),
+                            _p(index_out), _p(total_out), _p(err_out), _p(ws), _nbytes(ws),
+                            _stream(stream)), "qlc_encode")
+
+
+def qlc_compress(x: torch.Tensor, mode: int, table_out: torch.Tensor, chunk_symbols: int,
+                 bits_out: torch.Tensor, index_out: torch.Tensor, total_out: torch.Tensor,
+                 err_out: torch.Tensor, ws: torch.Tensor, stream=None, n: int | None = None):
+    n = x.numel() if n is None else n
+    _check(lib().qlc_compress(_p(x), n, mode, _p(table_out), chunk_symbols, _p(bits_out),
+                              _nbytes(bits_out), _p(index_out), _p(total_out), _p(err_out), _p(ws),
+                              _nbytes(ws), _stream(stream)), "qlc_compress")
+
+
+def qlc_decode(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor, chunk_symbols: int,
+               table: torch.Tensor, n: int, out: torch.Tensor, err_out: torch.Tensor,
+               ws: torch.Tensor, stream=None):
+    _check(lib().qlc_decode(_p(bits), _p(total), _p(index), chunk_symbols, _p(table), n, _p(out),
+                            _p(err_out), _p(ws), _nbytes(ws), _stream(stream)), "qlc_decode")
+
+
+def qlc_table_serialize(table_host: bytes | np.ndarray) -> bytes:
+    t = np.frombuffer(bytes(table_host), dtype=np.uint8).copy()
+    out = np.zeros(SERIALIZED_TABLE_BYTES, dtype=np.uint8)
+    _check(lib().qlc_table_serialize(t.ctypes.data, out.ctypes.data), "qlc_table_serialize")
+    return out.tobytes()
+
+
+def qlc_table_deserialize(blob: bytes) -> bytes:
+    b = np.frombuffer(bytes(blob), dtype=np.uint8).copy()
+    if b.size != SERIALIZED_TABLE_BYTES:
+        raise QLCError(QLC_ERR_INVALID_ARGUMENT, "qlc_table_deserialize")
+    out = np.zeros(TABLE_BYTES, dtype=np.uint8)
+    _check(lib().qlc_table_deserialize(b.ctypes.data, out.ctypes.data), "qlc_table_deserialize")
+    return out.tobytes()
+
+
+# ------------------------------------------------------------ helpers
+def parse_table(raw) -> dict:
+    """Decode the 1088 table bytes (host bytes or a device tensor) into numpy arrays."""
+    if isinstance(raw, torch.Tensor):
+        raw = raw.detach().cpu().numpy().tobytes()
+    t = _Table.from_buffer_copy(bytes(raw))
+    return dict(
+        enc=np.array(t.enc, dtype=np.int64), rank_to_sym=np.array(t.rank_to_sym, dtype=np.int64),
+        sym_to_rank=np.array(t.sym_to_rank, dtype=np.int64), width=np.array(t.width, np.int64),
+        offset=np.array(t.offset, np.int64), first=np.array(t.first, np.int64),
+        count=np.array(t.count, np.int64), cost_bits=int(t.cost_bits), mode=int(t.mode),
+        version=int(t.version))
+
+
+def new_table(device="cuda") -> torch.Tensor:
+    return torch.zeros(TABLE_BYTES, dtype=torch.uint8, device=device)
+
+
+def new_workspace(n: int, chunk_symbols: int = 4096, device="cuda") -> torch.Tensor:
+    """A zeroed workspace (torch allocations are 256-byte aligned)."""
+    return torch.zeros(qlc_workspace_bytes(n, chunk_symbols), dtype=torch.uint8, device=device)
+
+
+class Compressed:
+    """Device-resident compressed object: table, bitstream, chunk index."""
+
+    def __init__(self, n, chunk_symbols, table, bits, index, total, err):
+        self.n, self.chunk_symbols = n, chunk_symbols
+        self.table, self.bits, self.index, self.total, self.err = table, bits, index, total, err
+
+    def total_bits(self) -> int:
+        return int(self.total.item())
+
+    def nbytes(self) -> int:
+        return 4 * ((self.total_bits() + 31) // 32)
+
+
+def compress(x: torch.Tensor, mode: int = LAYOUT_SEARCH_QUAD, chunk_symbols: int = 4096,
+             table: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+             capacity: int | None = None) -> Compressed:
+    """Histogram + table (unless `table` is given) + encode, on the current stream."""
+    x = x.reshape(-1)
+    n = x.numel()
+    dev = x.device
+    ws = new_workspace(n, chunk_symbols, dev) if ws is None else ws
+    cap = qlc_encode_bound_bytes(n) if capacity is None else capacity
+    bits = torch.empty(max(cap, 16), dtype=torch.uint8, device=dev)[:cap]
+    index = torch.empty(max(qlc_chunk_count(n, chunk_symbols), 1), dtype=torch.int64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    if table is None:
+        table = new_table(dev)
+        qlc_compress(x, mode, table, chunk_symbols, bits, index, total, err, ws)
+    else:
+        qlc_encode(x, table, chunk_symbols, bits, index, total, err, ws)
+    return Compressed(n, chunk_symbols, table, bits, index, total, err)
+
+
+def decompress(c: Compressed, out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    dev = c.bits.device
+    out = torch.empty(max(c.n, 16), dtype=torch.uint8, device=dev)[:c.n] if out is None else out
+    err = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = new_workspace(0, c.chunk_symbols, dev) if ws is None else ws
+    qlc_decode(c.bits, c.total, c.index, c.chunk_symbols, c.table, c.n, out, err, ws)
+    return out, err

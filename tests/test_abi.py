@@ -1,0 +1,88 @@
+"""The C ABI library loads and exports every declared entry point; host-only
+entry points and argument validation behave as documented (CPU only: no
+call here reaches the GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import ROOT
+
+qlc = pytest.importorskip("paper_2602_17849_amd.qlc")
+
+
+def _declared_functions():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", hdr)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names.update(re.findall(r"\b(qlc_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(qlc.LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_size_queries():
+    assert qlc.qlc_chunk_count(0, 4096) == 0
+    assert qlc.qlc_chunk_count(4096, 4096) == 1
+    assert qlc.qlc_chunk_count(4097, 4096) == 2
+    for n in (0, 1, 31, 1000, 1 << 20):
+        b = qlc.qlc_encode_bound_bytes(n)
+        assert b % 16 == 0 and b >= 4 * ((11 * n + 31) // 32)
+    assert qlc.qlc_workspace_bytes(1 << 28, 4096) >= qlc.qlc_workspace_bytes(1 << 20, 4096)
+
+
+def test_argument_errors_are_synchronous():
+    L = qlc.lib()
+    ws = 1 << 20  # fake, 256-aligned device addresses: validation fails before any launch
+    big = 1 << 30
+    # chunk size not a power of two / out of range
+    for C in (0, 100, 128, 65536 * 2):
+        assert L.qlc_encode(ws, 10, ws, C, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+        assert L.qlc_decode(ws, ws, ws, C, ws, 10, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    # null input with n > 0, misaligned pointers, workspace too small, bad mode
+    assert L.qlc_encode(0, 10, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode(ws + 1, 10, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode(ws, 10, ws, 4096, ws, 64, ws, ws, ws, ws, 16, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_build_table(ws, 10, 9, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_histogram(0, 10, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_decode(ws, 0, ws, 4096, ws, 10, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode(ws, 1 << 36, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_host_table_deserialize_matches_oracle(seed):
+    """The library's host-side table builder agrees with the oracle's
+    table_from_layout on codes, lengths, areas and offsets."""
+    rng = np.random.default_rng(seed)
+    h = (rng.pareto(1.0, 256) * 100).astype(np.uint64)
+    ot = oracle.build_table(h, seed % 4)
+    blob = bytes(ot.width.astype(np.uint8)) + bytes(ot.rank_to_sym.astype(np.uint8))
+    t = qlc.parse_table(qlc.qlc_table_deserialize(blob))
+    assert list(t["width"]) == list(ot.width)
+    assert list(t["first"]) == list(ot.first) and list(t["count"]) == list(ot.count)
+    assert list(t["offset"]) == list(ot.offset)
+    assert list(t["rank_to_sym"]) == list(ot.rank_to_sym)
+    assert list(t["sym_to_rank"]) == list(ot.sym_to_rank)
+    assert list(t["enc"] >> 11) == list(ot.len)
+    assert list(t["enc"] & 0x7FF) == list(ot.code)
+    assert qlc.qlc_table_serialize(qlc.qlc_table_deserialize(blob)) == blob
+
+
+def test_host_table_deserialize_rejects_invalid():
+    perm = bytes(range(256))
+    for w in ([3] * 8, [5, 5, 5, 5, 5, 5, 4, 8], [9, 3, 3, 3, 3, 4, 5, 8], [5, 5, 5, 5, 5, 5, 6, 6]):
+        with pytest.raises(qlc.QLCError):
+            qlc.qlc_table_deserialize(bytes(w) + perm)
+    with pytest.raises(qlc.QLCError):
+        qlc.qlc_table_deserialize(bytes([3, 3, 3, 3, 3, 4, 5, 8]) + bytes([0]) + perm[1:255] + bytes([0]))

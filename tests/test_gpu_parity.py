@@ -1,0 +1,169 @@
+"""GPU parity: libqlc's HIP kernels against the CPU oracle, element by
+element, on seeded synthetic inputs (histogram, table, bitstream, chunk
+index, total bits, round trip, error codes).  Bit-exact throughout."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import paper_histogram
+from paper_2602_17849_amd import datagen, qlc
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import (DEV, assert_table_equal, gpu_decode, gpu_encode, gpu_table,  # noqa: E402
+                      table_from_oracle, to_dev)
+
+SIZES = [0, 1, 15, 16, 17, 255, 4095, 4096, 4097, 3 * 4096 + 1234, 100003, 262144 + 77]
+
+
+def _inputs(n, seed=0):
+    yield "gaussian", datagen.gaussian(n, seed).numpy() if n % 32 == 0 else \
+        np.resize(datagen.gaussian(((n + 31) // 32) * 32, seed).numpy(), n)
+    rng = np.random.default_rng(seed + n)
+    yield "uniform", rng.integers(0, 256, n).astype(np.uint8)
+    z = rng.integers(0, 256, n).astype(np.uint8)
+    z[rng.random(n) < 0.9] = 0
+    yield "zeros90", z
+    yield "constant", np.full(n, 0x5A, np.uint8)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_histogram(n):
+    for name, x in _inputs(n):
+        h = torch.zeros(256, dtype=torch.int64, device=DEV)
+        ws = qlc.new_workspace(n)
+        qlc.qlc_histogram(to_dev(x), h, ws)
+        assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.histogram(x)), name
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [0, 1, 4097, 100003, 1 << 20])
+def test_build_table(mode, n):
+    for name, x in _inputs(n, seed=1):
+        t = gpu_table(to_dev(x), mode)
+        assert_table_equal(t, oracle.build_table(oracle.histogram(x), mode))
+
+
+def test_table_from_histogram_paper_rows():
+    """Constructed histogram reproducing Tables 3/4 on the GPU, plus
+    histograms with many ties and counts beyond 2^32."""
+    h, _ = paper_histogram()
+    cases = [h, np.ones(256, np.uint64), np.repeat(np.arange(8, dtype=np.uint64), 32) * 5,
+             (np.arange(256, dtype=np.uint64) % 3) << np.uint64(34)]
+    for hh in cases:
+        for mode in range(4):
+            t = qlc.new_table()
+            qlc.qlc_table_from_histogram(to_dev(hh.astype(np.int64)), mode, t)
+            torch.cuda.synchronize()
+            assert_table_equal(t, oracle.build_table(hh, mode))
+
+
+@pytest.mark.parametrize("C", [256, 4096, 65536])
+@pytest.mark.parametrize("n", SIZES)
+def test_encode_bit_exact(n, C):
+    for name, x in _inputs(n, seed=2):
+        for mode in (0, 2):
+            ot = oracle.build_table(oracle.histogram(x), mode)
+            t = table_from_oracle(ot)
+            err, bits, nbytes, index, total = gpu_encode(to_dev(x), t, C)
+            st, obits, oindex, ototal = oracle.encode(x, ot, C)
+            assert err == 0 and st == 0
+            assert total == ototal
+            assert nbytes == obits.size
+            assert np.array_equal(bits[:nbytes], obits), (name, mode)
+            assert np.array_equal(index, oindex), (name, mode)
+
+
+@pytest.mark.parametrize("C", [256, 1024, 4096, 65536])
+@pytest.mark.parametrize("n", SIZES)
+def test_decode_oracle_streams(n, C):
+    """Decode streams written by the oracle (independent of the GPU encoder)."""
+    for name, x in _inputs(n, seed=3):
+        for mode in (0, 1, 2, 3):
+            ot = oracle.build_table(oracle.histogram(x), mode)
+            st, obits, oindex, ototal = oracle.encode(x, ot, C)
+            err, out = gpu_decode(obits, ototal, oindex, C, table_from_oracle(ot), n)
+            assert err == 0, (name, mode)
+            assert np.array_equal(out, x), (name, mode)
+
+
+def test_round_trip_gpu_only():
+    x = datagen.single_tensor_gaussian(seed=0, device=DEV)
+    c = qlc.compress(x, chunk_symbols=4096)
+    out, err = qlc.decompress(c)
+    torch.cuda.synchronize()
+    assert int(c.err.item()) == 0 and int(err.item()) == 0
+    assert torch.equal(out, x)
+
+
+def test_decode_error_codes_match_oracle():
+    rng = np.random.default_rng(4)
+    x = rng.integers(0, 256, 20000).astype(np.uint8)
+    C = 256
+    ot = oracle.build_table(oracle.histogram(x), oracle.MODE_PAPER_T1)
+    t = table_from_oracle(ot)
+    st, bits, index, total = oracle.encode(x, ot, C)
+    cases = {"truncated": (bits, total - 5, index, x.size)}
+    bad = index.copy(); bad[[3, 4]] = bad[[4, 3]]
+    cases["permuted_index"] = (bits, total, bad, x.size)
+    cases["short_n"] = (bits, total, index, x.size - 1)
+    bad0 = index.copy(); bad0[0] = 11
+    cases["index0"] = (bits, total, bad0, x.size)
+    for k in rng.integers(0, total, 12):
+        b2 = bits.copy(); b2[k // 8] ^= 0x80 >> (k % 8)
+        cases["flip%d" % k] = (b2, total, index, x.size)
+    for name, (b, tb, idx, n) in cases.items():
+        ost, oout = oracle.decode(b, tb, idx, C, ot, n)
+        err, out = gpu_decode(b, tb, idx, C, t, n)
+        assert err == ost, name
+        if ost == 0:
+            assert np.array_equal(out, oout), name
+
+
+def test_capacity_error():
+    x = datagen.gaussian(100000, 5).numpy()
+    ot = oracle.build_table(oracle.histogram(x), 0)
+    t = table_from_oracle(ot)
+    st, obits, oindex, ototal = oracle.encode(x, ot, 4096)
+    cap = (obits.size // 2) & ~15
+    err, bits, nbytes, index, total = gpu_encode(to_dev(x), t, 4096, cap=cap)
+    assert err == qlc.QLC_ERR_CAPACITY
+    assert total == ototal
+    assert np.array_equal(bits[:cap], obits[:cap])
+    assert not bits[cap:].any()          # nothing written past the capacity
+
+
+def test_deterministic_repeat():
+    x = to_dev(datagen.gaussian(1 << 20, 9).numpy())
+    t = gpu_table(x, 0)
+    a = gpu_encode(x, t, 1024)
+    for _ in range(3):
+        b = gpu_encode(x, t, 1024)
+        assert a[0] == b[0] and a[4] == b[4]
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("n", [0, 1, 4097, 100003, 5_000_013])
+@pytest.mark.parametrize("mode", [0, 3])
+def test_compress_fused(n, mode):
+    """Histogram + table + encode in one call (two kernels), against the
+    oracle's table and stream; sizes span several segments of different
+    lengths and a ragged tail."""
+    rng = np.random.default_rng(n + mode)
+    x = np.resize(datagen.gaussian(((n + 31) // 32) * 32 or 32, 7).numpy(), n)
+    x[rng.random(n) < 0.05] = rng.integers(0, 256)
+    xd = to_dev(x)
+    C = 1024
+    c = qlc.compress(xd, mode=mode, chunk_symbols=C)
+    torch.cuda.synchronize()
+    ot = oracle.build_table(oracle.histogram(x), mode)
+    assert_table_equal(c.table, ot)
+    st, obits, oindex, ototal = oracle.encode(x, ot, C)
+    assert int(c.err.item()) == 0
+    assert c.total_bits() == ototal
+    assert np.array_equal(c.bits[:obits.size].cpu().numpy(), obits)
+    assert np.array_equal(c.index[:oindex.size].cpu().numpy().astype(np.uint64), oindex)
+    out, err = qlc.decompress(c)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and np.array_equal(out.cpu().numpy(), x)
