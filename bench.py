@@ -1,0 +1,207 @@
+"""QLC codec benchmark on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--chunk C]
+
+One step = the whole hot path on one synthetic tensor already resident in
+HBM: histogram, rank, layout search and LUT emit (qlc_compress builds the
+table), bit-packed encode, then chunk-parallel decode of the stream.  The
+workload is the single 256 MiB e4m3 tensor (8192 x 32768, Laplace(0,1) with
+1 % of the rows scaled x8, block-32 power-of-two scaling, seed 1).
+
+Prints one JSON line.  `value` is uncompressed bytes per second of a whole
+step (N / (t_compress + t_decode)); per-kernel rates, the roofline of the
+dominant kernel and the CPU oracle baseline ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "QLC encode/decode GB/s (uncompressed) + % HBM peak; batched vs plain at bit-exact"
+WORKLOAD = ("single 256 MiB e4m3 tensor 8192x32768: FP32 Laplace(0,1), 1% rows x8, "
+            "block-32 power-of-two scale, RNE e4m3; per-tensor SEARCH_QUAD table; seed 1")
+KERNEL_SOURCES = ["paper_2602_17849_amd/csrc/qlc_kernels.hip",
+                  "paper_2602_17849_amd/csrc/qlc_device.h",
+                  "paper_2602_17849_amd/csrc/qlc_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM traffic per launch measured by rocprofv3 counters (profiles/),
+    valid only while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(x_host, chunk, budget_s=20.0):
+    """The CPU oracle (single-threaded C) on a bounded prefix sample of the
+    same tensor: histogram + table + encode + decode, timed on the host."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    n_sample = 1 << 22  # 4 Mi symbols
+    xs = np.ascontiguousarray(x_host[:n_sample])
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        h = oracle.histogram(xs)
+        t = oracle.build_table(h, oracle.MODE_SEARCH_QUAD)
+        st, bits, index, total = oracle.encode(xs, t, chunk)
+        st2, out = oracle.decode(bits, total, index, chunk, t, xs.size)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s / 4 or reps >= 3:
+            break
+    assert st == 0 and st2 == 0 and np.array_equal(out, xs)
+    rate = reps * xs.size / el / 1e9
+    return {"value": round(rate, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d symbols of the workload tensor, %d repetition(s) of "
+                      "histogram+table+encode+decode, %.1f s" % (xs.size, reps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chunk", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(each tensor shard is compressed independently on its own GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2602_17849_amd import datagen, qlc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x = datagen.single_tensor_laplace(device=dev)
+    n = x.numel()
+    C = args.chunk
+    ws = qlc.new_workspace(n, C, dev)
+    table = qlc.new_table(dev)
+    cap = qlc.qlc_encode_bound_bytes(n)
+    bits = torch.empty(cap, dtype=torch.uint8, device=dev)
+    index = torch.empty(qlc.qlc_chunk_count(n, C), dtype=torch.int64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    derr = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        qlc.qlc_compress(x, qlc.LAYOUT_SEARCH_QUAD, table, C, bits, index, total, err, ws)
+        if ev is not None:
+            ev[1].record(stream)
+        qlc.qlc_decode(bits, total, index, C, table, n, out, derr, ws)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and int(derr.item()) == 0
+    assert torch.equal(out, x), "round trip mismatch"
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert int(err.item()) == 0 and int(derr.item()) == 0
+    t_comp = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
+    t_dec = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
+    ms_per_step = wall / args.steps * 1e3
+
+    # per-kernel rates: encode with the table fixed, histogram+table alone
+    def timed(fn, reps=10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    t_enc = timed(lambda: qlc.qlc_encode(x, table, C, bits, index, total, err, ws))
+    t_tab = timed(lambda: qlc.qlc_build_table(x, qlc.LAYOUT_SEARCH_QUAD, table, ws))
+    torch.cuda.synchronize()
+    tb = int(total.item())
+    L = tb / n
+    stream_bytes = 4 * ((tb + 31) // 32)
+    index_bytes = 8 * qlc.qlc_chunk_count(n, C)
+    # algorithmic bytes of one decode launch: read stream + index, write symbols
+    dec_bytes = stream_bytes + index_bytes + n
+    achieved = dec_bytes / t_dec / 1e9
+    traffic = load_traffic("k_decode")
+
+    res = {
+        "metric": METRIC,
+        "value": round(n / (t_comp + t_dec) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "symbols": n, "chunk_symbols": C,
+                   "layout_mode": "SEARCH_QUAD"},
+        "compress_gbps": round(n / t_comp / 1e9, 2),
+        "decode_gbps": round(n / t_dec / 1e9, 2),
+        "encode_fixed_table_gbps": round(n / t_enc / 1e9, 2),
+        "build_table_gbps": round(n / t_tab / 1e9, 2),
+        "bits_per_symbol": round(L, 5),
+        "compressibility": round((8 - L) / 8, 5),
+        "compressibility_with_index_and_table": round(
+            1 - (stream_bytes + index_bytes + 264) / n, 5),
+        "roofline": {"kernel": "k_decode", "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dec_bytes},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), C)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
