@@ -15,7 +15,7 @@ constexpr int kTableThreads = 512;    // table-building workgroup
 constexpr int kEncThreads = 256;      // encode workgroup
 constexpr int kEncSymsPerThread = 16; // one 16-byte load per thread
 constexpr int kEncTile = kEncThreads * kEncSymsPerThread;  // symbols per tile
-constexpr int kDecThreads = 256;      // decode workgroup: one lane per chunk
+constexpr int kDecThreads = 128;      // decode workgroup: one lane per chunk
 constexpr int kDecGroup = 8;          // symbols decoded per window refill
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies
 

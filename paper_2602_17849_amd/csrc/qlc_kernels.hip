@@ -438,45 +438,71 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // Decode (Implementation section: 3 bits give the area and thus the suffix
 // width; suffix + offset = rank; rank -> symbol via the decoder LUT).
 //
-// One lane per chunk.  The decoder LUT is re-indexed by the whole code
-// word: because widths never decrease, the codes of area a occupy the
-// integer range [a << w_a, (a + 1) << w_a) and these ranges are disjoint,
-// so a 2048-entry LDS table maps code -> symbol (bit 15 flags an invalid
-// suffix).  The per-symbol chain is pure VALU: the 3-bit area code selects
-// the shift 29 - w_a from an 8-byte register table (v_perm), the code is
-// the window shifted right by it, and three funnel shifts advance a 96-bit
-// window by 3 + w_a bits.
+// One lane per chunk, 128 chunks per workgroup.  The decoder LUT is
+// re-indexed by the whole code word: because widths never decrease, the
+// codes of area a occupy the integer range [a << w_a, (a + 1) << w_a) and
+// these ranges are disjoint, so a 2048-entry LDS table maps code -> symbol
+// (bit 15 flags an invalid suffix).  The per-symbol chain is pure VALU: the
+// 3-bit area code selects the shift 29 - w_a from an 8-byte register table
+// (v_perm), the code is the window shifted right by it, and three funnel
+// shifts advance a 96-bit window by 3 + w_a bits.
 //
-// Each lane streams its chunk through a private 8-block LDS ring (16-byte
-// blocks, plus a mirror of block 0 so a 4-word window never wraps).  Blocks
-// are fetched with bounds-checked buffer loads, at most one per 8-symbol
-// group, and written into the ring two groups after their load was issued
-// (two alternating register buffers), so the load latency hides behind two
-// groups of decoding of every wave on the SIMD.  Lanes that need no block
-// still issue the load with an out-of-range offset (returns zeros, touches
-// no memory) so that every wave waits at a fixed program point.
+// Memory: each lane streams its chunk in 64-byte superblocks (four 16-byte
+// bounds-checked buffer loads of one aligned 64-byte line segment) into a
+// private 2-superblock LDS ring (plus a mirror of the first words, so a
+// 4-word window never wraps).  A superblock is loaded at most once per
+// 8-symbol group and written to the ring two groups after its load was
+// issued (two alternating register sets), so every wave waits at fixed
+// program points for loads that are two groups old.  Lanes that need no
+// superblock issue the loads with an out-of-range offset (zeros returned,
+// no memory touched).  Decoded bytes are staged per lane in LDS and, every
+// 8 groups, the wave stores all 64 lanes' 64-byte output runs with
+// coalesced stores (8 lanes per 64-byte run).
 // ===========================================================================
-constexpr int kRingStride = 36;          // 32 ring words + 4 mirror words (144 B)
-constexpr uint32_t kLookaheadBits = 512;
-constexpr uint32_t kOobOffset = 0xFFFFFFF0u;
+constexpr int kDecLanes = kDecThreads;     // chunks per workgroup
+constexpr int kRingStride = 36;            // 2 x 16 ring words + 4 mirror words
+constexpr uint32_t kLookaheadBits = 384;
+constexpr uint32_t kOobOffset = 0xFFFFFFC0u;
 constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
 
 struct DecSmem {
   uint16_t lut[2048];
-  uint32_t ring[kDecThreads * kRingStride];
+  uint32_t ring[kDecLanes * kRingStride];
+  uint2 stage[kDecLanes * 8];               // 8 groups x 8 bytes per lane
 };
 
-__device__ __forceinline__ uint4 load_block(__amdgpu_buffer_rsrc_t rsrc, uint32_t off) {
+struct Superblock {
+  uint4 q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ uint4 bufload16(__amdgpu_buffer_rsrc_t rsrc, uint32_t off) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
   return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-__device__ __forceinline__ void ring_put(uint32_t* ring, uint64_t blk, uint4 v) {
-  const uint32_t slot = (uint32_t)(blk & 7u) * 4u;
-  const uint4 w = make_uint4(__builtin_bswap32(v.x), __builtin_bswap32(v.y),
-                             __builtin_bswap32(v.z), __builtin_bswap32(v.w));
-  *reinterpret_cast<uint4*>(ring + slot) = w;
-  if (slot == 0) *reinterpret_cast<uint4*>(ring + 32) = w;
+__device__ __forceinline__ Superblock load_sb(__amdgpu_buffer_rsrc_t rsrc, uint32_t off) {
+  Superblock s;
+  s.q0 = bufload16(rsrc, off);
+  s.q1 = bufload16(rsrc, off + 16);
+  s.q2 = bufload16(rsrc, off + 32);
+  s.q3 = bufload16(rsrc, off + 48);
+  return s;
+}
+
+__device__ __forceinline__ uint4 bswap4(uint4 v) {
+  return make_uint4(__builtin_bswap32(v.x), __builtin_bswap32(v.y), __builtin_bswap32(v.z),
+                    __builtin_bswap32(v.w));
+}
+
+// Superblock `sb` (absolute number) into ring slot sb & 1 (words 16*(sb&1)).
+__device__ __forceinline__ void ring_put(uint32_t* ring, uint32_t sb, const Superblock& s) {
+  uint4* r = reinterpret_cast<uint4*>(ring + (sb & 1u) * 16u);
+  const uint4 a = bswap4(s.q0);
+  r[0] = a;
+  r[1] = bswap4(s.q1);
+  r[2] = bswap4(s.q2);
+  r[3] = bswap4(s.q3);
+  if ((sb & 1u) == 0) *reinterpret_cast<uint4*>(ring + 32) = a;
 }
 
 struct DecLane {
@@ -491,7 +517,7 @@ __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __rest
   const uint32_t q = (uint32_t)L.pm1;
   const uint32_t wi = (q >> 5) & 31u;
   const uint32_t w0 = L.ring[wi], w1 = L.ring[wi + 1], w2 = L.ring[wi + 2], w3 = L.ring[wi + 3];
-  const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - ((pos) & 31), or 0
+  const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - (pos & 31), or 0
   uint32_t A = __builtin_amdgcn_alignbit(w0, w1, sh0);
   uint32_t B = __builtin_amdgcn_alignbit(w1, w2, sh0);
   uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, sh0);
@@ -522,6 +548,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
   __shared__ DecSmem S;
   const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63;
   const uint64_t total = *total_p;
 
   // ---- code -> symbol LUT and the per-area shift table ----
@@ -561,95 +588,124 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
   bool bad = false;
 
   if (j_wave < nchunks) {
-    // Buffer resource rebased at the wave's first chunk: loads past the end
-    // of the stream (or through a corrupt index) return zeros.
+    // Buffer resource rebased at the wave's first chunk (64-byte aligned):
+    // loads past the end of the stream, or through a corrupt index, return
+    // zeros.
     const uint64_t stream_bytes = ((total + 31) >> 5) << 2;
     const uint64_t wave_bit = index[j_wave];
-    const uint64_t base_blk =
-        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 7)) |
-        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 39)) << 32);
-    const uint64_t base_byte = base_blk << 4;
+    const uint64_t base_sb =
+        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 9)) |
+        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 41)) << 32);
+    const uint64_t base_byte = base_sb << 6;
     uint64_t avail = stream_bytes > base_byte ? stream_bytes - base_byte : 0;
     if (avail > kOobOffset) avail = kOobOffset;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(bits + (base_byte < stream_bytes ? base_byte : 0)), (short)0,
         (int)(uint32_t)avail, 0x00020000);
 
+    // Per-lane state.  Lanes past the last chunk, or whose index entries
+    // are inconsistent, decode nothing but still take part in the wave's
+    // uniform refill / flush schedule.
+    uint32_t my_groups = 0, rem = 0;
+    uint64_t pos0 = 0, end = 0;
     if (j < nchunks) {
-      const uint64_t pos0 = index[j];
-      const uint64_t end = (j + 1 < nchunks) ? index[j + 1] : total;
+      pos0 = index[j];
+      end = (j + 1 < nchunks) ? index[j + 1] : total;
       const uint64_t left = n - (j << log2_chunk);
       const uint32_t nsym = (uint32_t)(left < C ? left : C);
       if (pos0 > end || end > total || (j == 0 && pos0 != 0) || pos0 < wave_bit ||
-          ((pos0 >> 7) - base_blk) > (kOobOffset >> 4) - 64) {
+          ((pos0 >> 9) - base_sb) > (kOobOffset >> 6) - 1024) {
         bad = true;
       } else {
-        DecLane L;
-        L.ring = S.ring + tid * kRingStride;
-        L.pm1 = pos0 - 1;
-        L.sh_lo = sh_lo;
-        L.sh_hi = sh_hi;
-        L.errbits = 0;
-        uint32_t fb = (uint32_t)((pos0 >> 7) - base_blk);  // next block to fetch (wave-relative)
-        const uint32_t bb0 = (uint32_t)base_blk;  // ring slots follow absolute block numbers
-        {
-          uint4 pre[5];
-#pragma unroll
-          for (int b = 0; b < 5; ++b) pre[b] = load_block(rsrc, (fb + b) << 4);
-#pragma unroll
-          for (int b = 0; b < 5; ++b) ring_put(L.ring, bb0 + fb + b, pre[b]);
-        }
-        fb += 5;
-        // wave-relative bit position of the next symbol, for the refill test
-        const uint64_t rel0 = base_blk << 7;
-        uint4 pa = make_uint4(0, 0, 0, 0), pb = pa;
-        uint32_t ba = 0, bb = 0;
-        bool va = false, vb = false;
-        uint8_t* o = out + (j << log2_chunk);
-        const uint32_t groups = nsym >> 3;
-        uint32_t g = 0;
-        for (; g + 2 <= groups; g += 2) {
-          *reinterpret_cast<uint2*>(o + g * 8) = decode_group(L, S.lut);
-          if (va) ring_put(L.ring, bb0 + ba, pa);
-          va = ((uint64_t)fb << 7) < (L.pm1 + 1 - rel0) + kLookaheadBits;
-          ba = fb;
-          pa = load_block(rsrc, va ? (fb << 4) : kOobOffset);
-          fb += va ? 1u : 0u;
-          *reinterpret_cast<uint2*>(o + g * 8 + 8) = decode_group(L, S.lut);
-          if (vb) ring_put(L.ring, bb0 + bb, pb);
-          vb = ((uint64_t)fb << 7) < (L.pm1 + 1 - rel0) + kLookaheadBits;
-          bb = fb;
-          pb = load_block(rsrc, vb ? (fb << 4) : kOobOffset);
-          fb += vb ? 1u : 0u;
-        }
-        if (va) ring_put(L.ring, bb0 + ba, pa);
-        if (vb) ring_put(L.ring, bb0 + bb, pb);
-        if (g < groups) {  // odd number of groups (last chunk only)
-          *reinterpret_cast<uint2*>(o + g * 8) = decode_group(L, S.lut);
-          ++g;
-        }
-        const uint32_t rem = nsym - groups * 8;
-        if (rem) {  // final partial group of the last chunk
-          const uint32_t q = (uint32_t)L.pm1;
-          const uint32_t wi = (q >> 5) & 31u;
-          uint32_t A = __builtin_amdgcn_alignbit(L.ring[wi], L.ring[wi + 1], ~q);
-          uint32_t B = __builtin_amdgcn_alignbit(L.ring[wi + 1], L.ring[wi + 2], ~q);
-          uint32_t Cw = __builtin_amdgcn_alignbit(L.ring[wi + 2], L.ring[wi + 3], ~q);
-          for (uint32_t k = 0; k < rem; ++k) {
-            const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
-            const uint32_t s = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
-            const uint32_t e = S.lut[A >> s];
-            L.errbits |= e;
-            o[groups * 8 + k] = (uint8_t)e;
-            A = __builtin_amdgcn_alignbit(A, B, s);
-            B = __builtin_amdgcn_alignbit(B, Cw, s);
-            Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
-            L.pm1 += 32u - s;
-          }
-        }
-        bad = (L.errbits & 0x8000u) || (L.pm1 + 1 != end);
+        my_groups = nsym >> 3;
+        rem = nsym & 7;
       }
     }
+    const bool live = (j < nchunks) && !bad;
+    DecLane L;
+    L.ring = S.ring + tid * kRingStride;
+    L.pm1 = (live ? pos0 : 0) - 1;
+    L.sh_lo = sh_lo;
+    L.sh_hi = sh_hi;
+    L.errbits = 0;
+    const uint32_t sb0 = (uint32_t)base_sb;         // ring slots follow absolute superblocks
+    uint32_t fsb = live ? (uint32_t)((pos0 >> 9) - base_sb) : 0;  // next superblock (wave-relative)
+    {
+      const Superblock p0 = load_sb(rsrc, live ? (fsb << 6) : kOobOffset);
+      const Superblock p1 = load_sb(rsrc, live ? ((fsb + 1) << 6) : kOobOffset);
+      ring_put(L.ring, sb0 + fsb, p0);
+      ring_put(L.ring, sb0 + fsb + 1, p1);
+      fsb += 2;
+    }
+    const uint64_t rel0 = base_sb << 9;
+    Superblock pa, pb;
+    uint32_t sba = 0, sbb = 0;
+    bool va = false, vb = false;
+    uint2* stage = S.stage + tid * 8;
+    uint8_t* o = out + (j << log2_chunk);
+    // all lanes of the wave run the same number of groups
+    const uint32_t wave_groups = (uint32_t)(C >> 3);
+
+#define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
+  {                                                                                     \
+    const uint32_t gg = (gidx);                                                         \
+    if (gg < my_groups) stage[(gg ^ tid) & 7u] = decode_group(L, S.lut);                \
+    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
+    VAL = live && gg < my_groups &&                                                     \
+          ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
+    SBX = fsb;                                                                          \
+    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    fsb += VAL ? 1u : 0u;                                                               \
+  }
+
+    for (uint32_t g = 0; g < wave_groups; g += 8) {
+      QLC_DEC_GROUP(g + 0, va, sba, pa)
+      QLC_DEC_GROUP(g + 1, vb, sbb, pb)
+      QLC_DEC_GROUP(g + 2, va, sba, pa)
+      QLC_DEC_GROUP(g + 3, vb, sbb, pb)
+      QLC_DEC_GROUP(g + 4, va, sba, pa)
+      QLC_DEC_GROUP(g + 5, vb, sbb, pb)
+      QLC_DEC_GROUP(g + 6, va, sba, pa)
+      QLC_DEC_GROUP(g + 7, vb, sbb, pb)
+      // Flush: 64 lanes x 64 bytes; 8 consecutive lanes write one lane's
+      // 64-byte run (8 bytes each) so every store instruction covers whole
+      // 64-byte segments.
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
+        const uint32_t part = lane & 7u;                      // 8-byte piece of the run
+        const uint32_t stid = (tid & ~63u) | src;
+        const uint2 v = S.stage[stid * 8 + ((part ^ stid) & 7u)];
+        const uint64_t jj = (uint64_t)blockIdx.x * kDecThreads + stid;
+        const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
+        if (g + part < ngrp)
+          *reinterpret_cast<uint2*>(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8) = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+#undef QLC_DEC_GROUP
+    if (va) ring_put(L.ring, sb0 + sba, pa);
+    if (vb) ring_put(L.ring, sb0 + sbb, pb);
+    if (live && rem) {  // final partial group of the last chunk
+      const uint32_t q = (uint32_t)L.pm1;
+      const uint32_t wi = (q >> 5) & 31u;
+      uint32_t A = __builtin_amdgcn_alignbit(L.ring[wi], L.ring[wi + 1], ~q);
+      uint32_t B = __builtin_amdgcn_alignbit(L.ring[wi + 1], L.ring[wi + 2], ~q);
+      uint32_t Cw = __builtin_amdgcn_alignbit(L.ring[wi + 2], L.ring[wi + 3], ~q);
+      for (uint32_t k = 0; k < rem; ++k) {
+        const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
+        const uint32_t s = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
+        const uint32_t e = S.lut[A >> s];
+        L.errbits |= e;
+        o[my_groups * 8 + k] = (uint8_t)e;
+        A = __builtin_amdgcn_alignbit(A, B, s);
+        B = __builtin_amdgcn_alignbit(B, Cw, s);
+        Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
+        L.pm1 += 32u - s;
+      }
+    }
+    if (live) bad = (L.errbits & 0x8000u) || (L.pm1 + 1 != end);
   }
 
   // ---- error word: first error wins; the last workgroup publishes it ----
