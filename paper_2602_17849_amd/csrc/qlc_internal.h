@@ -13,7 +13,7 @@ constexpr int kHistThreads = 512;     // histogram workgroup
 constexpr int kHistCopies = 32;       // LDS sub-histograms (one per lane mod 32)
 constexpr int kTableThreads = 512;    // table-building workgroup
 constexpr int kEncThreads = 256;      // encode workgroup
-constexpr int kEncSymsPerThread = 16; // one 16-byte load per thread
+constexpr int kEncSymsPerThread = 32; // two 16-byte loads per thread
 constexpr int kEncTile = kEncThreads * kEncSymsPerThread;  // symbols per tile
 constexpr int kDecThreads = 128;      // decode workgroup: one lane per chunk
 constexpr int kDecGroup = 8;          // symbols decoded per window refill
@@ -49,7 +49,7 @@ constexpr size_t kWsSegOffset = kWsHistOffset + kWsHistBytes;     // u32[nseg][2
 // Segments: the unit of the histogram and encode grids, a power of two of
 // at least one encode tile, about 1024 of them for large inputs.
 inline uint32_t seg_log2(uint64_t n) {
-  uint32_t l = 12;                                   // 4096 symbols
+  uint32_t l = 13;                                   // 8192 symbols (one tile)
   while (l < 20 && (n >> l) > 1024) ++l;             // ... up to 1 Mi symbols
   while ((n >> l) > (1ull << 24)) ++l;               // keep the grid bounded
   return l;

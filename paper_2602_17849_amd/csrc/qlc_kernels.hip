@@ -271,14 +271,8 @@ struct EncSmem {
   uint32_t words[kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
   uint64_t red[kEncThreads / 64];
   uint32_t wave_sum[kEncThreads / 64];
-  uint32_t seg, epoch, cap_hit;
-  uint64_t prefix;
+  uint32_t seg, epoch, cap_hit, bad_table;
 };
-
-__device__ __forceinline__ uint32_t clamp_len(uint32_t e) {
-  const uint32_t l = e >> 11;  // <= 11 in any valid table; the clamp guards LDS bounds
-  return l < QLC_MAX_CODE_BITS ? l : QLC_MAX_CODE_BITS;
-}
 
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   v = wave_sum_u64(v);
@@ -290,6 +284,26 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   __syncthreads();
   return t;
 }
+
+// Append code `c` of `l` bits to the thread's run in the LDS word buffer
+// (64-bit accumulator, a whole word is OR-ed out whenever 32 bits are due;
+// the caller guarantees nacc + l <= 63).
+struct Packer {
+  uint64_t acc;
+  uint32_t nacc, widx;
+  __device__ __forceinline__ void put(uint32_t* words, uint32_t c, uint32_t l) {
+    acc = (acc << l) | c;
+    nacc += l;
+    if (nacc >= 32) {
+      nacc -= 32;
+      atomicOr(&words[widx], (uint32_t)(acc >> nacc));
+      ++widx;
+    }
+  }
+  __device__ __forceinline__ void finish(uint32_t* words) {
+    if (nacc) atomicOr(&words[widx], (uint32_t)(acc << (32 - nacc)));
+  }
+};
 
 __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
@@ -305,18 +319,24 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     S.seg = atomic_add_u32(&hdr->enc_ticket, 1u);
     S.epoch = load_relaxed_u32(&hdr->enc_epoch) & kEpochMask;
     S.cap_hit = 0;
+    S.bad_table = 0;
   }
   const uint32_t e_t = table->enc[tid];
   S.lut[tid] = (uint16_t)e_t;
+  for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) S.words[w] = 0;
   __syncthreads();
+  // A table whose code lengths leave 3..11 is rejected (keeps every LDS
+  // index of the packer in bounds without per-symbol clamps).
+  if ((e_t >> 11) < 3 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.bad_table = 1;
   const uint32_t seg = S.seg;
   const uint32_t epoch = S.epoch;
   const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
 
   // ---- this segment's bit count, published; the predecessors' summed ----
   const uint64_t my_bits =
-      block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * clamp_len(e_t), S.red);
-  if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | my_bits);
+      block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
+  const bool bad_table = S.bad_table != 0;
+  if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
   uint64_t pre = 0;
   for (uint32_t k = tid; k < seg; k += kEncThreads) {
     uint64_t w;
@@ -328,94 +348,134 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   const uint64_t G = block_sum_u64(pre, S.red);
   if (seg == nseg - 1 && tid == 0) *total_out = G + my_bits;
 
-  // ---- last bits of the previous segment (recomputed from its input) ----
   const uint64_t seg0 = (uint64_t)seg << log2_seg;
-  uint32_t carry = 0;  // bits [G & ~31, G) of the stream, MSB aligned
-  if ((G & 31) != 0) {
-    uint64_t acc = 0;
-    for (int k = 16; k >= 1; --k) {
-      const uint32_t e = S.lut[in[seg0 - k]];
-      acc = (acc << clamp_len(e)) | (e & 0x7FFu);
-    }
-    const uint32_t g = (uint32_t)(G & 31);
-    carry = ((uint32_t)acc) << (32 - g);
-  }
-
-  // ---- tiles of 4096 symbols ----
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
   const bool last_seg = (seg == nseg - 1);
-  uint64_t R = G;  // global bit offset of the current tile
   bool cap = false;
-  for (uint64_t t0 = seg0; t0 < seg1 || (t0 == seg0 && seg1 == seg0); t0 += kEncTile) {
-    const uint64_t base = t0 + (uint64_t)tid * kEncSymsPerThread;
-    uint32_t sw[4] = {0, 0, 0, 0};
-    uint32_t nv = 0;
-    if (base + kEncSymsPerThread <= seg1) {
-      const uint4 v = *reinterpret_cast<const uint4*>(in + base);
-      sw[0] = v.x; sw[1] = v.y; sw[2] = v.z; sw[3] = v.w;
-      nv = kEncSymsPerThread;
-    } else if (base < seg1) {
-      nv = (uint32_t)(seg1 - base);
-      for (uint32_t k = 0; k < nv; ++k) sw[k >> 2] |= (uint32_t)in[base + k] << (8 * (k & 3));
-    }
-    uint32_t code[kEncSymsPerThread], len[kEncSymsPerThread];
-    uint32_t mybits = 0;
-#pragma unroll
-    for (int k = 0; k < kEncSymsPerThread; ++k) {
-      const uint32_t e = S.lut[(sw[k >> 2] >> (8 * (k & 3))) & 0xFFu];
-      const bool valid = (uint32_t)k < nv;
-      len[k] = valid ? clamp_len(e) : 0u;
-      code[k] = valid ? (e & 0x7FFu) : 0u;
-      mybits += len[k];
-    }
-    // block exclusive scan of the per-thread bit counts
-    const uint32_t incl = wave_inclusive_scan_u32(mybits);
-    if (lane == 63) S.wave_sum[wave] = incl;
-    const uint32_t g = (uint32_t)(R & 31);
-    // zero the tile's word buffer, word 0 starts with the carried bits
-    for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) S.words[w] = w ? 0u : carry;
-    __syncthreads();
-    uint32_t wave_off = 0, tile_bits = 0;
-#pragma unroll
-    for (int w = 0; w < kEncThreads / 64; ++w) {
-      const uint32_t ws = S.wave_sum[w];
-      wave_off += (w < (int)wave) ? ws : 0u;
-      tile_bits += ws;
-    }
-    const uint32_t off = wave_off + incl - mybits;
-    // pack this thread's codes at bit g + off of the tile buffer, MSB first
-    {
+  if (!bad_table) {
+    // ---- last bits of the previous segment (recomputed from its input) ----
+    if ((G & 31) != 0 && tid == 0) {
       uint64_t acc = 0;
-      uint32_t nacc = (g + off) & 31u;
-      uint32_t widx = (g + off) >> 5;
+      for (int k = 16; k >= 1; --k) {
+        const uint32_t e = S.lut[in[seg0 - k]];
+        acc = (acc << (e >> 11)) | (e & 0x7FFu);
+      }
+      S.words[0] = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
+    }
+    uint64_t R = G;  // global bit offset of the current tile
+    const uint64_t cmask = (1ull << log2_chunk) - 1;
+    uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
+    if (seg0 + kEncTile <= seg1) {
+      const uint4* p = reinterpret_cast<const uint4*>(in + seg0 + (uint64_t)tid * 16);
+      nx0 = p[0];
+      nx1 = p[kEncThreads];
+    }
+    for (uint64_t t0 = seg0;; t0 += kEncTile) {
+      const bool full = t0 + kEncTile <= seg1;
+      uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (full tiles)
+      uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
+      if (full) {
+        const uint4 v0 = nx0, v1 = nx1;
+        if (t0 + 2 * kEncTile <= seg1) {  // prefetch the next tile
+          const uint4* p = reinterpret_cast<const uint4*>(in + t0 + kEncTile + (uint64_t)tid * 16);
+          nx0 = p[0];
+          nx1 = p[kEncThreads];
+        }
+        const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-      for (int k = 0; k < kEncSymsPerThread; ++k) {
-        acc = (acc << len[k]) | code[k];
-        nacc += len[k];
-        if (nacc >= 32) {
-          nacc -= 32;
-          atomicOr(&S.words[widx], (uint32_t)(acc >> nacc));
-          ++widx;
+        for (int k = 0; k < 16; ++k) {
+          const uint32_t w = sw[k >> 1];
+          const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
+          const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
+          const uint32_t l1 = e1 >> 11;
+          pc[k] = ((e0 & 0x7FFu) << l1) | (e1 & 0x7FFu);
+          pl[k] = (e0 >> 11) + l1;
+          if (k < 8) b0 += pl[k];
+          else b1 += pl[k];
+        }
+      } else {
+        // the input's ragged last tile: symbols [t0, seg1)
+#pragma unroll 1
+        for (int k = 0; k < 32; ++k) {
+          const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+          const uint32_t l = i < seg1 ? ((uint32_t)S.lut[in[i]] >> 11) : 0u;
+          if (k < 16) b0 += l;
+          else b1 += l;
         }
       }
-      if (nacc) atomicOr(&S.words[widx], (uint32_t)(acc << (32 - nacc)));
+      // Thread tid owns two runs of the tile: symbols 16*tid.. (first half)
+      // and 4096+16*tid.. (second half), so that its loads are coalesced.
+      // Every first-half run precedes every second-half run in the stream;
+      // one block scan of the packed pair (b0 | b1 << 16) places both
+      // (run bits <= 176, block totals < 2^16).
+      const uint32_t packed = b0 | (b1 << 16);
+      const uint32_t incl = wave_inclusive_scan_u32(packed);
+      if (lane == 63) S.wave_sum[wave] = incl;
+      __syncthreads();
+      uint32_t o = 0, h = 0;
+#pragma unroll
+      for (int w = 0; w < kEncThreads / 64; ++w) {
+        const uint32_t ws = S.wave_sum[w];
+        o += (w < (int)wave) ? ws : 0u;
+        h += ws;
+      }
+      const uint32_t h0 = h & 0xFFFFu, h1 = h >> 16;
+      const uint32_t tile_bits = h0 + h1;
+      const uint32_t g = (uint32_t)(R & 31);
+      const uint32_t off0 = (o & 0xFFFFu) + (incl & 0xFFFFu) - b0;
+      const uint32_t off1 = h0 + (o >> 16) + (incl >> 16) - b1;
+      {
+        Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
+        Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
+        if (full) {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
+#pragma unroll
+          for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
+        } else {
+#pragma unroll 1
+          for (int k = 0; k < 32; ++k) {
+            const uint64_t i =
+                t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+            if (i < seg1) {
+              const uint32_t e = S.lut[in[i]];
+              if (k < 16) P0.put(S.words, e & 0x7FFu, e >> 11);
+              else P1.put(S.words, e & 0x7FFu, e >> 11);
+            }
+          }
+        }
+        P0.finish(S.words);
+        P1.finish(S.words);
+        // chunk index entries: a run's first symbol may start a chunk
+        const uint64_t i0s = t0 + (uint64_t)tid * 16;
+        const uint64_t i1s = i0s + kEncTile / 2;
+        if (i0s < seg1 && (i0s & cmask) == 0) index_out[i0s >> log2_chunk] = R + off0;
+        if (i1s < seg1 && (i1s & cmask) == 0) index_out[i1s >> log2_chunk] = R + off1;
+      }
+      __syncthreads();
+      // store the whole words (and, at the very end, the padded last word),
+      // clearing them for the next tile
+      const uint32_t endb = g + tile_bits;
+      const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
+      const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
+      const uint64_t w0 = R >> 5;
+      for (uint32_t i = tid; i < nw; i += kEncThreads) {
+        if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
+        else cap = true;
+        S.words[i] = 0;
+      }
+      __syncthreads();
+      if (tid == 0 && !final_tile) {
+        // the partial last word becomes word 0 of the next tile
+        const uint32_t carry = S.words[endb >> 5];
+        S.words[endb >> 5] = 0;
+        S.words[0] = carry;
+      }
+      R += tile_bits;
+      if (t0 + kEncTile >= seg1) break;
     }
-    if (base < seg1 && (base & ((1ull << log2_chunk) - 1)) == 0)
-      index_out[base >> log2_chunk] = R + off;
-    __syncthreads();
-    // store the whole words (and, at the very end, the padded last word)
-    const uint32_t endb = g + tile_bits;
-    const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
-    const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
-    const uint64_t w0 = R >> 5;
-    for (uint32_t i = tid; i < nw; i += kEncThreads) {
-      if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
-      else cap = true;
-    }
-    carry = S.words[endb >> 5];  // partial last word (garbage-free: zero padded)
-    R += tile_bits;
-    __syncthreads();
-    if (seg1 == seg0) break;  // empty input: one pass with no symbols
+  } else if (tid == 0) {
+    set_error(&hdr->enc_err, QLC_ERR_INVALID_ARGUMENT);
   }
   if (cap) S.cap_hit = 1;
   __syncthreads();
@@ -489,20 +549,15 @@ __device__ __forceinline__ Superblock load_sb(__amdgpu_buffer_rsrc_t rsrc, uint3
   return s;
 }
 
-__device__ __forceinline__ uint4 bswap4(uint4 v) {
-  return make_uint4(__builtin_bswap32(v.x), __builtin_bswap32(v.y), __builtin_bswap32(v.z),
-                    __builtin_bswap32(v.w));
-}
-
-// Superblock `sb` (absolute number) into ring slot sb & 1 (words 16*(sb&1)).
+// Superblock `sb` (absolute number) into ring slot sb & 1 (words 16*(sb&1)),
+// in memory byte order (the window reads swap to most-significant-first).
 __device__ __forceinline__ void ring_put(uint32_t* ring, uint32_t sb, const Superblock& s) {
   uint4* r = reinterpret_cast<uint4*>(ring + (sb & 1u) * 16u);
-  const uint4 a = bswap4(s.q0);
-  r[0] = a;
-  r[1] = bswap4(s.q1);
-  r[2] = bswap4(s.q2);
-  r[3] = bswap4(s.q3);
-  if ((sb & 1u) == 0) *reinterpret_cast<uint4*>(ring + 32) = a;
+  r[0] = s.q0;
+  r[1] = s.q1;
+  r[2] = s.q2;
+  r[3] = s.q3;
+  if ((sb & 1u) == 0) *reinterpret_cast<uint4*>(ring + 32) = s.q0;
 }
 
 struct DecLane {
@@ -516,7 +571,8 @@ struct DecLane {
 __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
   const uint32_t q = (uint32_t)L.pm1;
   const uint32_t wi = (q >> 5) & 31u;
-  const uint32_t w0 = L.ring[wi], w1 = L.ring[wi + 1], w2 = L.ring[wi + 2], w3 = L.ring[wi + 3];
+  const uint32_t w0 = __builtin_bswap32(L.ring[wi]), w1 = __builtin_bswap32(L.ring[wi + 1]);
+  const uint32_t w2 = __builtin_bswap32(L.ring[wi + 2]), w3 = __builtin_bswap32(L.ring[wi + 3]);
   const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - (pos & 31), or 0
   uint32_t A = __builtin_amdgcn_alignbit(w0, w1, sh0);
   uint32_t B = __builtin_amdgcn_alignbit(w1, w2, sh0);
@@ -646,6 +702,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
 
+#define QLC_DEC_REFILL(VAL, SBX, PX)                                                    \
+  {                                                                                     \
+    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
+    VAL = ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
+    SBX = fsb;                                                                          \
+    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    fsb += VAL ? 1u : 0u;                                                               \
+  }
 #define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
   {                                                                                     \
     const uint32_t gg = (gidx);                                                         \
@@ -658,41 +722,68 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     fsb += VAL ? 1u : 0u;                                                               \
   }
 
-    for (uint32_t g = 0; g < wave_groups; g += 8) {
-      QLC_DEC_GROUP(g + 0, va, sba, pa)
-      QLC_DEC_GROUP(g + 1, vb, sbb, pb)
-      QLC_DEC_GROUP(g + 2, va, sba, pa)
-      QLC_DEC_GROUP(g + 3, vb, sbb, pb)
-      QLC_DEC_GROUP(g + 4, va, sba, pa)
-      QLC_DEC_GROUP(g + 5, vb, sbb, pb)
-      QLC_DEC_GROUP(g + 6, va, sba, pa)
-      QLC_DEC_GROUP(g + 7, vb, sbb, pb)
-      // Flush: 64 lanes x 64 bytes; 8 consecutive lanes write one lane's
-      // 64-byte run (8 bytes each) so every store instruction covers whole
-      // 64-byte segments.
-      __builtin_amdgcn_wave_barrier();
+    // Waves whose 64 chunks are all whole and valid (all but at most the
+    // last wave) take a branch-free path.
+    const bool full_wave = __all(live && my_groups == wave_groups);
+    if (full_wave) {
+      uint8_t* obase = out + ((j_wave + (lane >> 3)) << log2_chunk) + (lane & 7u) * 8u;
+      for (uint32_t g = 0; g < wave_groups; g += 8) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
-        const uint32_t part = lane & 7u;                      // 8-byte piece of the run
-        const uint32_t stid = (tid & ~63u) | src;
-        const uint2 v = S.stage[stid * 8 + ((part ^ stid) & 7u)];
-        const uint64_t jj = (uint64_t)blockIdx.x * kDecThreads + stid;
-        const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
-        if (g + part < ngrp)
-          *reinterpret_cast<uint2*>(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8) = v;
+        for (int k = 0; k < 8; k += 2) {
+          stage[((g + k) ^ tid) & 7u] = decode_group(L, S.lut);
+          QLC_DEC_REFILL(va, sba, pa)
+          stage[((g + k + 1) ^ tid) & 7u] = decode_group(L, S.lut);
+          QLC_DEC_REFILL(vb, sbb, pb)
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t stid = (tid & ~63u) | ((lane >> 3) + 8u * k);
+          const uint2 v = S.stage[stid * 8 + ((lane ^ stid) & 7u)];
+          *reinterpret_cast<uint2*>(obase + ((uint64_t)(8 * k) << log2_chunk) + g * 8) = v;
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      __builtin_amdgcn_wave_barrier();
+    } else {
+      for (uint32_t g = 0; g < wave_groups; g += 8) {
+        QLC_DEC_GROUP(g + 0, va, sba, pa)
+        QLC_DEC_GROUP(g + 1, vb, sbb, pb)
+        QLC_DEC_GROUP(g + 2, va, sba, pa)
+        QLC_DEC_GROUP(g + 3, vb, sbb, pb)
+        QLC_DEC_GROUP(g + 4, va, sba, pa)
+        QLC_DEC_GROUP(g + 5, vb, sbb, pb)
+        QLC_DEC_GROUP(g + 6, va, sba, pa)
+        QLC_DEC_GROUP(g + 7, vb, sbb, pb)
+        // Flush: 64 lanes x 64 bytes; 8 consecutive lanes write one lane's
+        // 64-byte run (8 bytes each) so every store instruction covers
+        // whole 64-byte segments.
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
+          const uint32_t part = lane & 7u;                      // 8-byte piece of the run
+          const uint32_t stid = (tid & ~63u) | src;
+          const uint2 v = S.stage[stid * 8 + ((part ^ stid) & 7u)];
+          const uint64_t jj = (uint64_t)blockIdx.x * kDecThreads + stid;
+          const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
+          if (g + part < ngrp)
+            *reinterpret_cast<uint2*>(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8) = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
     }
+#undef QLC_DEC_REFILL
 #undef QLC_DEC_GROUP
     if (va) ring_put(L.ring, sb0 + sba, pa);
     if (vb) ring_put(L.ring, sb0 + sbb, pb);
     if (live && rem) {  // final partial group of the last chunk
       const uint32_t q = (uint32_t)L.pm1;
       const uint32_t wi = (q >> 5) & 31u;
-      uint32_t A = __builtin_amdgcn_alignbit(L.ring[wi], L.ring[wi + 1], ~q);
-      uint32_t B = __builtin_amdgcn_alignbit(L.ring[wi + 1], L.ring[wi + 2], ~q);
-      uint32_t Cw = __builtin_amdgcn_alignbit(L.ring[wi + 2], L.ring[wi + 3], ~q);
+      const uint32_t w0 = __builtin_bswap32(L.ring[wi]), w1 = __builtin_bswap32(L.ring[wi + 1]);
+      const uint32_t w2 = __builtin_bswap32(L.ring[wi + 2]), w3 = __builtin_bswap32(L.ring[wi + 3]);
+      uint32_t A = __builtin_amdgcn_alignbit(w0, w1, ~q);
+      uint32_t B = __builtin_amdgcn_alignbit(w1, w2, ~q);
+      uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, ~q);
       for (uint32_t k = 0; k < rem; ++k) {
         const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
         const uint32_t s = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
