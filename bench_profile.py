@@ -157,7 +157,7 @@ if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "copy":
         copy_workload()
     else:
-        chunk = 1024
+        chunk = 2048
         if "--chunk" in sys.argv:
             chunk = int(sys.argv[sys.argv.index("--chunk") + 1])
         os.chdir("/tmp")

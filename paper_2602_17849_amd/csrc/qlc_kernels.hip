@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // ===========================================================================
 constexpr int kDecLanes = kDecThreads;     // chunks per workgroup
 constexpr int kRingStride = 36;            // 2 x 16 ring words + 4 mirror words
-constexpr uint32_t kLookaheadBits = 384;
+constexpr uint32_t kLookaheadBits = 512;
 constexpr uint32_t kOobOffset = 0xFFFFFFC0u;
 constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
 
@@ -698,6 +698,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     uint32_t sba = 0, sbb = 0;
     bool va = false, vb = false;
     uint2* stage = S.stage + tid * 8;
+    const uint32_t sw = tid >> 2;  // staging slot swizzle: 2-way LDS bank sharing at most
     uint8_t* o = out + (j << log2_chunk);
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
@@ -713,7 +714,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
 #define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
   {                                                                                     \
     const uint32_t gg = (gidx);                                                         \
-    if (gg < my_groups) stage[(gg ^ tid) & 7u] = decode_group(L, S.lut);                \
+    if (gg < my_groups) stage[(gg ^ sw) & 7u] = decode_group(L, S.lut);                 \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
     VAL = live && gg < my_groups &&                                                     \
           ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
@@ -723,27 +724,39 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
   }
 
     // Waves whose 64 chunks are all whole and valid (all but at most the
-    // last wave) take a branch-free path.
+    // last wave) take a branch-free path with four register sets in
+    // rotation: a superblock is written to the ring four groups after its
+    // load was issued.  Every 8 groups the wave stores its 64 lanes'
+    // 64-byte output runs, 8 consecutive lanes per run.
     const bool full_wave = __all(live && my_groups == wave_groups);
     if (full_wave) {
+      Superblock pc_, pd_;
+      uint32_t sbc = 0, sbd = 0;
+      bool vc = false, vd = false;
       uint8_t* obase = out + ((j_wave + (lane >> 3)) << log2_chunk) + (lane & 7u) * 8u;
-      for (uint32_t g = 0; g < wave_groups; g += 8) {
+#pragma unroll 1
+      for (uint32_t g = 0; g < wave_groups; g += 4) {
+        stage[((g + 0) ^ sw) & 7u] = decode_group(L, S.lut);
+        QLC_DEC_REFILL(va, sba, pa)
+        stage[((g + 1) ^ sw) & 7u] = decode_group(L, S.lut);
+        QLC_DEC_REFILL(vb, sbb, pb)
+        stage[((g + 2) ^ sw) & 7u] = decode_group(L, S.lut);
+        QLC_DEC_REFILL(vc, sbc, pc_)
+        stage[((g + 3) ^ sw) & 7u] = decode_group(L, S.lut);
+        QLC_DEC_REFILL(vd, sbd, pd_)
+        if ((g & 7u) == 4u) {
+          __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < 8; k += 2) {
-          stage[((g + k) ^ tid) & 7u] = decode_group(L, S.lut);
-          QLC_DEC_REFILL(va, sba, pa)
-          stage[((g + k + 1) ^ tid) & 7u] = decode_group(L, S.lut);
-          QLC_DEC_REFILL(vb, sbb, pb)
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t stid = (tid & ~63u) | ((lane >> 3) + 8u * k);
+            const uint2 v = S.stage[stid * 8 + (((lane & 7u) ^ (stid >> 2)) & 7u)];
+            *reinterpret_cast<uint2*>(obase + ((uint64_t)(8 * k) << log2_chunk) + (g - 4) * 8) = v;
+          }
+          __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t stid = (tid & ~63u) | ((lane >> 3) + 8u * k);
-          const uint2 v = S.stage[stid * 8 + ((lane ^ stid) & 7u)];
-          *reinterpret_cast<uint2*>(obase + ((uint64_t)(8 * k) << log2_chunk) + g * 8) = v;
-        }
-        __builtin_amdgcn_wave_barrier();
       }
+      if (vc) ring_put(L.ring, sb0 + sbc, pc_);
+      if (vd) ring_put(L.ring, sb0 + sbd, pd_);
     } else {
       for (uint32_t g = 0; g < wave_groups; g += 8) {
         QLC_DEC_GROUP(g + 0, va, sba, pa)
@@ -754,16 +767,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
         QLC_DEC_GROUP(g + 5, vb, sbb, pb)
         QLC_DEC_GROUP(g + 6, va, sba, pa)
         QLC_DEC_GROUP(g + 7, vb, sbb, pb)
-        // Flush: 64 lanes x 64 bytes; 8 consecutive lanes write one lane's
-        // 64-byte run (8 bytes each) so every store instruction covers
-        // whole 64-byte segments.
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
           const uint32_t part = lane & 7u;                      // 8-byte piece of the run
           const uint32_t stid = (tid & ~63u) | src;
-          const uint2 v = S.stage[stid * 8 + ((part ^ stid) & 7u)];
+          const uint2 v = S.stage[stid * 8 + ((part ^ (stid >> 2)) & 7u)];
           const uint64_t jj = (uint64_t)blockIdx.x * kDecThreads + stid;
           const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
           if (g + part < ngrp)
