@@ -171,6 +171,70 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits,
                       uint32_t* err_out, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* ---- Batched form: many tensors (shards) of uneven sizes per launch ----
+ *
+ * The same steps as qlc_compress / qlc_decode applied to every job of a
+ * device array; each job's table, bitstream, index and total are
+ * byte-identical to what the single-tensor entry points produce for it with
+ * the same mode and C.  A call is a small planning kernel followed by one
+ * persistent launch whose workgroups take work items (segment histograms,
+ * table builds, segment encodes, or 128-chunk decode groups) from a shared
+ * queue, so small shards do not leave the device idle.  Neither call
+ * allocates, synchronises or sets memory from the host, so both may be
+ * captured in a hipGraph and replayed. */
+typedef struct qlc_job {
+  const uint8_t* in;       /* encode: n input symbols (16-B aligned)           */
+  uint8_t* out;            /* decode: n output symbols (16-B aligned)          */
+  uint64_t n;              /* symbols of the job (< 2^36)                      */
+  qlc_table* table;        /* encode: built when build_table, else read;
+                              decode: read (16-B aligned)                      */
+  uint8_t* bits;           /* encode: written; decode: read (16-B aligned)     */
+  uint64_t bits_capacity;  /* encode: bytes writable at bits                   */
+  uint64_t* chunk_index;   /* ceil(n / C) entries (8-B aligned)                */
+  uint64_t* total_bits;    /* encode: written; decode: read (8-B aligned)      */
+  uint32_t* err;           /* the job's status, set by every call (4-B aligned) */
+  uint32_t build_table;    /* encode: 1 = build *table from `in` with `mode`   */
+  uint32_t reserved;       /* 0 */
+} qlc_job;                 /* 80 bytes */
+
+/* Work split of a batched call; zero fields take the defaults. */
+typedef struct qlc_batch_tuning {
+  uint32_t log2_segment; /* encode work item = 2^log2_segment symbols, 13..24
+                            (default 18) */
+  uint32_t lag_segments; /* encode: histogram items handed out ahead of the
+                            encode items, raised to the largest job's segment
+                            count (0: every histogram first) */
+  uint32_t workgroups;   /* persistent workgroups (0: fill the device)        */
+  uint32_t reserved;     /* 0 */
+} qlc_batch_tuning;
+
+/* Workspace bytes for batched calls over n_jobs jobs holding at most
+ * total_symbols symbols together (h_tuning may be NULL).  The workspace is
+ * zeroed once before first use (qlc_workspace_init) and must not be shared
+ * with the single-tensor entry points without zeroing it again. */
+size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols,
+                                   uint32_t chunk_symbols,
+                                   const qlc_batch_tuning* h_tuning);
+
+/* Steps 1-5 for every job of the device array `jobs` (n_jobs entries).  Per
+ * job: *err = 0 on success; QLC_ERR_INVALID_ARGUMENT for a job whose
+ * pointers are NULL or misaligned, n >= 2^36, reserved != 0, or (for every
+ * job) when the workspace is too small for the jobs' total size; a job
+ * whose err pointer is NULL or misaligned is skipped.  QLC_ERR_CAPACITY as
+ * qlc_encode.  A table written by a build_table job must not be another
+ * job's table in the same call. */
+qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs,
+                              qlc_layout_mode mode, uint32_t chunk_symbols,
+                              const qlc_batch_tuning* h_tuning, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Step 6 for every job of `jobs` (bits, chunk_index, total_bits and table
+ * in, out written); per-job err as qlc_decode. */
+qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs,
+                              uint32_t chunk_symbols,
+                              const qlc_batch_tuning* h_tuning, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+
 /* Host-side persisted table form: width[8] followed by rank_to_sym[256]. */
 qlc_status qlc_table_serialize(const qlc_table* h_table,
                                uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]);

@@ -57,6 +57,61 @@ WsView carve(void* ws, uint64_t n) {
   return v;
 }
 
+// ---- batched calls ----
+constexpr uint64_t kMaxBatchUnits = 1ull << 30;
+
+struct BatchView {
+  BatchHeader* hdr;
+  BatchJobState* js;
+  uint64_t* job_hist;
+  uint32_t* seg_hist;   // encode
+  uint64_t* seg_word;   // encode
+  uint32_t* unit_job;   // seg_job (encode) or grp_job (decode)
+  uint64_t max_units;
+};
+
+BatchView carve_batch(void* ws, size_t ws_bytes, uint32_t n_jobs, bool decode) {
+  char* b = static_cast<char*>(ws);
+  BatchView v{};
+  v.hdr = reinterpret_cast<BatchHeader*>(b);
+  v.js = reinterpret_cast<BatchJobState*>(b + batch_js_offset());
+  v.job_hist = reinterpret_cast<uint64_t*>(b + batch_hist_offset(n_jobs));
+  const size_t u0 = batch_units_offset(n_jobs);
+  const size_t room = ws_bytes > u0 ? ws_bytes - u0 : 0;
+  uint64_t mu = room / (decode ? kBatchGroupBytes : kBatchSegBytes);
+  if (mu > kMaxBatchUnits) mu = kMaxBatchUnits;
+  v.max_units = mu;
+  if (decode) {
+    v.unit_job = reinterpret_cast<uint32_t*>(b + u0);
+  } else {
+    v.seg_hist = reinterpret_cast<uint32_t*>(b + u0);
+    v.seg_word = reinterpret_cast<uint64_t*>(b + u0 + mu * 256 * sizeof(uint32_t));
+    v.unit_job = reinterpret_cast<uint32_t*>(b + u0 + mu * (256 * sizeof(uint32_t) + 8));
+  }
+  return v;
+}
+
+bool batch_tuning(const qlc_batch_tuning* t, uint32_t* log2_seg, uint32_t* lag, uint32_t* wgs) {
+  *log2_seg = kBatchDefaultLog2Seg;
+  *lag = 0;
+  *wgs = 0;
+  if (!t) return true;
+  if (t->reserved) return false;
+  if (t->log2_segment) {
+    if (t->log2_segment < kBatchMinLog2Seg || t->log2_segment > kBatchMaxLog2Seg) return false;
+    *log2_seg = t->log2_segment;
+  }
+  *lag = t->lag_segments;
+  *wgs = t->workgroups;
+  return true;
+}
+
+uint32_t persistent_grid(bool decode, uint32_t requested) {
+  if (requested) return requested;
+  const uint32_t g = (uint32_t)(device_cus() * batched_blocks_per_cu(decode));
+  return g ? g : 1;
+}
+
 }  // namespace
 }  // namespace qlc
 
@@ -197,6 +252,53 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits, const uin
   WsView v = carve(ws, 0);
   return hip_status(launch_decode(bits, total_bits, chunk_index, log2c, table, n, out, err_out,
                                   v.hdr, stream));
+}
+
+size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint32_t chunk_symbols,
+                                   const qlc_batch_tuning* h_tuning) {
+  uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
+  if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
+    return 0;
+  const uint64_t segs = (total_symbols >> log2_seg) + n_jobs;
+  const uint64_t groups = (total_symbols >> (log2c + 7)) + n_jobs;
+  const uint64_t enc = segs * kBatchSegBytes, dec = groups * kBatchGroupBytes;
+  return round256(batch_units_offset(n_jobs) + (enc > dec ? enc : dec));
+}
+
+qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_mode mode,
+                              uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
+  if (!valid_chunk(chunk_symbols, &log2c) || (uint32_t)mode > QLC_LAYOUT_PAPER_T2 ||
+      !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
+    return QLC_ERR_INVALID_ARGUMENT;
+  if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
+  if (n_jobs == 0) return QLC_OK;
+  if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
+  BatchView v = carve_batch(ws, ws_bytes, n_jobs, false);
+  hipError_t e = launch_batch_plan(jobs, n_jobs, false, log2_seg, v.max_units, lag, v.hdr, v.js,
+                                   v.unit_job, v.seg_word, stream);
+  if (e != hipSuccess) return QLC_ERR_HIP;
+  return hip_status(launch_encode_batched(jobs, (uint32_t)mode, log2_seg, log2c, v.hdr, v.js,
+                                          v.job_hist, v.unit_job, v.seg_word, v.seg_hist,
+                                          persistent_grid(false, wgs), stream));
+}
+
+qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chunk_symbols,
+                              const qlc_batch_tuning* h_tuning, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
+  if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
+    return QLC_ERR_INVALID_ARGUMENT;
+  if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
+  if (n_jobs == 0) return QLC_OK;
+  if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
+  BatchView v = carve_batch(ws, ws_bytes, n_jobs, true);
+  hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + 7, v.max_units, 0, v.hdr, v.js,
+                                   v.unit_job, nullptr, stream);
+  if (e != hipSuccess) return QLC_ERR_HIP;
+  return hip_status(launch_decode_batched(jobs, log2c, v.hdr, v.js, v.unit_job,
+                                          persistent_grid(true, wgs), stream));
 }
 
 qlc_status qlc_table_serialize(const qlc_table* h_table, uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]) {

@@ -67,4 +67,39 @@ inline size_t ws_bytes_for(uint64_t n) {
   return (b + 255) & ~size_t(255);
 }
 
+// ---- batched workspace -----------------------------------------------------
+// [BatchHeader][BatchJobState x jobs][uint64 hist[256] x jobs][per-unit arrays]
+// Units are encode segments (seg_hist u32[256], seg_word u64, seg_job u32
+// each) or decode chunk groups (grp_job u32 each).
+struct BatchHeader {
+  uint32_t ticket;  // next work item of the persistent launch
+  uint32_t units;   // segments (encode) or chunk groups (decode) of all jobs
+  uint32_t lag;     // encode: histogram items handed out ahead of encode items
+  uint32_t abort;   // the plan found the workspace too small
+  uint32_t pad[60];
+};
+static_assert(sizeof(BatchHeader) == 256, "batch header size");
+
+struct BatchJobState {
+  uint32_t base;         // first unit of the job
+  uint32_t count;        // units of the job (0: job skipped)
+  uint32_t hist_done;    // encode: histogram items finished
+  uint32_t table_ready;  // encode: all histograms in (and the table built)
+};
+
+constexpr uint32_t kBatchDefaultLog2Seg = 18;
+constexpr uint32_t kBatchMinLog2Seg = 13;
+constexpr uint32_t kBatchMaxLog2Seg = 24;
+constexpr size_t kBatchSegBytes = 256 * sizeof(uint32_t) + sizeof(uint64_t) + sizeof(uint32_t);
+constexpr size_t kBatchGroupBytes = sizeof(uint32_t);
+
+inline size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+inline size_t batch_js_offset() { return sizeof(BatchHeader); }
+inline size_t batch_hist_offset(uint32_t jobs) {
+  return batch_js_offset() + round256((size_t)jobs * sizeof(BatchJobState));
+}
+inline size_t batch_units_offset(uint32_t jobs) {
+  return batch_hist_offset(jobs) + (size_t)jobs * 256 * sizeof(uint64_t);
+}
+
 }  // namespace qlc

@@ -19,6 +19,18 @@ hipError_t launch_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
 hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint64_t* index,
                          uint32_t log2_chunk, const qlc_table* table, uint64_t n, uint8_t* out,
                          uint32_t* err_out, WsHeader* hdr, hipStream_t stream);
+hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
+                             uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
+                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream);
+hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t mode, uint32_t log2_seg,
+                                 uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
+                                 uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,
+                                 uint32_t* seg_hist, uint32_t grid, hipStream_t stream);
+hipError_t launch_decode_batched(const qlc_job* jobs, uint32_t log2_chunk, BatchHeader* hdr,
+                                 const BatchJobState* js, const uint32_t* grp_job, uint32_t grid,
+                                 hipStream_t stream);
+// Workgroups of a batched kernel that fit on one compute unit at once.
+int batched_blocks_per_cu(bool decode);
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t stream);
 
 }  // namespace qlc

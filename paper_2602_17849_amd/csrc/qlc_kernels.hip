@@ -24,10 +24,15 @@ struct TableSmem {
   uint32_t r2s[256];        // rank -> symbol
   uint32_t width[8], first[8], count[8], offset[8];
   uint64_t cost;
+  qlc_table stage;          // the table is assembled here, then copied out
 };
 
-__device__ void build_table_block(const uint64_t* h_in, uint32_t mode,
-                                  qlc_table* out, TableSmem& S) {
+// kCoherent: copy the table out with device-coherent stores, for readers
+// in other workgroups of the same launch (the batched encoder).
+template <bool kCoherent>
+__device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t mode,
+                                  qlc_table* out_g, TableSmem& S) {
+  qlc_table* out = &S.stage;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
   for (int s = tid; s < 256; s += nt) S.h[s] = h_in[s];
@@ -144,12 +149,20 @@ __device__ void build_table_block(const uint64_t* h_in, uint32_t mode,
     out->mode = mode;
     out->version = QLC_ABI_VERSION;
   }
+  __syncthreads();
+  static_assert(sizeof(qlc_table) % 4 == 0, "table words");
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&S.stage);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(out_g);
+  for (int w = tid; w < (int)(sizeof(qlc_table) / 4); w += nt) {
+    if (kCoherent) store_relaxed_u32(&dst[w], src[w]);
+    else dst[w] = src[w];
+  }
 }
 
 __global__ __launch_bounds__(kTableThreads) void k_table_from_hist(
     const uint64_t* __restrict__ hist, uint32_t mode, qlc_table* __restrict__ out) {
   __shared__ TableSmem S;
-  build_table_block(hist, mode, out, S);
+  build_table_block<false>(hist, mode, out, S);
 }
 
 // ===========================================================================
@@ -184,6 +197,38 @@ __device__ __forceinline__ void hist_add_vec(uint32_t* sub, uint4 v, uint32_t co
   hist_add_word(sub, v.w, copy);
 }
 
+// Count bytes [seg0, seg1) of `in` into the 32 LDS copies (zeroed by the
+// caller); seg0 is a multiple of 16.
+__device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uint64_t seg0,
+                                             uint64_t seg1, uint32_t* sub, uint32_t tid) {
+  const uint32_t nt = blockDim.x;
+  const uint32_t copy = tid & (kHistCopies - 1);
+  const uint4* vin = reinterpret_cast<const uint4*>(in);
+  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
+  uint64_t i = v0 + tid;
+  for (; i + 3 * nt < v1; i += 4 * nt) {
+    const uint4 a = vin[i];
+    const uint4 b = vin[i + nt];
+    const uint4 c = vin[i + 2 * nt];
+    const uint4 d = vin[i + 3 * nt];
+    hist_add_vec(sub, a, copy);
+    hist_add_vec(sub, b, copy);
+    hist_add_vec(sub, c, copy);
+    hist_add_vec(sub, d, copy);
+  }
+  for (; i < v1; i += nt) hist_add_vec(sub, vin[i], copy);
+  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += nt)  // ragged tail of the input
+    atomicAdd(&sub[((uint32_t)in[j] << 5) | copy], 1u);
+}
+
+// Per-bin total of the 32 copies (thread t < 256 sums bin t).
+__device__ __forceinline__ uint32_t hist_bin_total(const uint32_t* sub, uint32_t t) {
+  uint32_t s = 0;
+#pragma unroll 8
+  for (uint32_t c = 0; c < kHistCopies; ++c) s += sub[(t << 5) | ((c + t) & 31)];
+  return s;
+}
+
 __global__ __launch_bounds__(kHistThreads) void k_histogram(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg, WsHeader* __restrict__ hdr,
     uint64_t* __restrict__ xcd_part, uint32_t* __restrict__ seg_hist,
@@ -195,31 +240,13 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
   for (uint32_t i = tid; i < 256 * kHistCopies; i += kHistThreads) S.sub[i] = 0;
   __syncthreads();
 
-  const uint32_t copy = tid & (kHistCopies - 1);
   const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
-  const uint4* vin = reinterpret_cast<const uint4*>(in);
-  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
-  uint64_t i = v0 + tid;
-  for (; i + 3 * kHistThreads < v1; i += 4 * kHistThreads) {
-    const uint4 a = vin[i];
-    const uint4 b = vin[i + kHistThreads];
-    const uint4 c = vin[i + 2 * kHistThreads];
-    const uint4 d = vin[i + 3 * kHistThreads];
-    hist_add_vec(S.sub, a, copy);
-    hist_add_vec(S.sub, b, copy);
-    hist_add_vec(S.sub, c, copy);
-    hist_add_vec(S.sub, d, copy);
-  }
-  for (; i < v1; i += kHistThreads) hist_add_vec(S.sub, vin[i], copy);
-  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += kHistThreads)  // ragged tail of the input
-    atomicAdd(&S.sub[((uint32_t)in[j] << 5) | copy], 1u);
+  hist_segment(in, seg0, seg1, S.sub, tid);
   __syncthreads();
 
   if (tid < 256) {
-    uint32_t s = 0;
-#pragma unroll 8
-    for (uint32_t c = 0; c < kHistCopies; ++c) s += S.sub[(tid << 5) | ((c + tid) & 31)];
+    const uint32_t s = hist_bin_total(S.sub, tid);
     if (flags & kHistSegment) seg_hist[(uint64_t)blockIdx.x * 256 + tid] = s;
     if ((flags & kHistGlobal) && s)
       atomicAdd((unsigned long long*)&xcd_part[(blockIdx.x % kNumXcd) * 256 + tid],
@@ -247,7 +274,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
   }
   if (tid == 0) store_relaxed_u32(&hdr->hist_done, 0);
   __syncthreads();
-  if (flags & kHistBuildTable) build_table_block(hsum, mode, table_out, S.table);
+  if (flags & kHistBuildTable) build_table_block<false>(hsum, mode, table_out, S.table);
 }
 
 // ===========================================================================
@@ -305,6 +332,148 @@ struct Packer {
   }
 };
 
+// Encode symbols [seg0, seg1) of `in`, whose first code starts at stream
+// bit G (kEncThreads threads, tid = threadIdx.x).  On entry S.lut holds the encoder LUT and
+// S.words[1..] are zero; on return S.words[1..] are zero again.  Every
+// whole stream word of the segment is stored; its partial first word also
+// carries the previous segment's last bits (recomputed from the 16 symbols
+// before seg0); its partial last word is left to the next segment, unless
+// `last_seg` (padded and stored).  Returns true in a thread one of whose
+// stores would have passed cap_words (that store is dropped).
+__device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, uint64_t seg0, uint64_t seg1,
+                               uint64_t G, bool last_seg, uint32_t log2_chunk,
+                               uint32_t* __restrict__ bits_out, uint64_t cap_words,
+                               uint64_t* __restrict__ index_out, EncSmem& S, uint32_t tid) {
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  bool cap = false;
+  // ---- last bits of the previous segment (recomputed from its input) ----
+  if (tid == 0) {
+    uint32_t w0 = 0;
+    if ((G & 31) != 0) {
+      uint64_t acc = 0;
+      for (int k = 16; k >= 1; --k) {
+        const uint32_t e = S.lut[in[seg0 - k]];
+        acc = (acc << (e >> 11)) | (e & 0x7FFu);
+      }
+      w0 = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
+    }
+    S.words[0] = w0;
+  }
+  uint64_t R = G;  // global bit offset of the current tile
+  const uint64_t cmask = (1ull << log2_chunk) - 1;
+  uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
+  if (seg0 + kEncTile <= seg1) {
+    const uint4* p = reinterpret_cast<const uint4*>(in + seg0 + (uint64_t)tid * 16);
+    nx0 = p[0];
+    nx1 = p[kEncThreads];
+  }
+  for (uint64_t t0 = seg0;; t0 += kEncTile) {
+    const bool full = t0 + kEncTile <= seg1;
+    uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (full tiles)
+    uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
+    if (full) {
+      const uint4 v0 = nx0, v1 = nx1;
+      if (t0 + 2 * kEncTile <= seg1) {  // prefetch the next tile
+        const uint4* p = reinterpret_cast<const uint4*>(in + t0 + kEncTile + (uint64_t)tid * 16);
+        nx0 = p[0];
+        nx1 = p[kEncThreads];
+      }
+      const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t w = sw[k >> 1];
+        const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
+        const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
+        const uint32_t l1 = e1 >> 11;
+        pc[k] = ((e0 & 0x7FFu) << l1) | (e1 & 0x7FFu);
+        pl[k] = (e0 >> 11) + l1;
+        if (k < 8) b0 += pl[k];
+        else b1 += pl[k];
+      }
+    } else {
+      // the input's ragged last tile: symbols [t0, seg1)
+#pragma unroll 1
+      for (int k = 0; k < 32; ++k) {
+        const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+        const uint32_t l = i < seg1 ? ((uint32_t)S.lut[in[i]] >> 11) : 0u;
+        if (k < 16) b0 += l;
+        else b1 += l;
+      }
+    }
+    // Thread tid owns two runs of the tile: symbols 16*tid.. (first half)
+    // and 4096+16*tid.. (second half), so that its loads are coalesced.
+    // Every first-half run precedes every second-half run in the stream;
+    // one block scan of the packed pair (b0 | b1 << 16) places both
+    // (run bits <= 176, block totals < 2^16).
+    const uint32_t packed = b0 | (b1 << 16);
+    const uint32_t incl = wave_inclusive_scan_u32(packed);
+    if (lane == 63) S.wave_sum[wave] = incl;
+    __syncthreads();
+    uint32_t o = 0, h = 0;
+#pragma unroll
+    for (int w = 0; w < kEncThreads / 64; ++w) {
+      const uint32_t ws = S.wave_sum[w];
+      o += (w < (int)wave) ? ws : 0u;
+      h += ws;
+    }
+    const uint32_t h0 = h & 0xFFFFu, h1 = h >> 16;
+    const uint32_t tile_bits = h0 + h1;
+    const uint32_t g = (uint32_t)(R & 31);
+    const uint32_t off0 = (o & 0xFFFFu) + (incl & 0xFFFFu) - b0;
+    const uint32_t off1 = h0 + (o >> 16) + (incl >> 16) - b1;
+    {
+      Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
+      Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
+      if (full) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
+#pragma unroll
+        for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
+      } else {
+#pragma unroll 1
+        for (int k = 0; k < 32; ++k) {
+          const uint64_t i =
+              t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+          if (i < seg1) {
+            const uint32_t e = S.lut[in[i]];
+            if (k < 16) P0.put(S.words, e & 0x7FFu, e >> 11);
+            else P1.put(S.words, e & 0x7FFu, e >> 11);
+          }
+        }
+      }
+      P0.finish(S.words);
+      P1.finish(S.words);
+      // chunk index entries: a run's first symbol may start a chunk
+      const uint64_t i0s = t0 + (uint64_t)tid * 16;
+      const uint64_t i1s = i0s + kEncTile / 2;
+      if (i0s < seg1 && (i0s & cmask) == 0) index_out[i0s >> log2_chunk] = R + off0;
+      if (i1s < seg1 && (i1s & cmask) == 0) index_out[i1s >> log2_chunk] = R + off1;
+    }
+    __syncthreads();
+    // store the whole words (and, at the very end, the padded last word),
+    // clearing them for the next tile
+    const uint32_t endb = g + tile_bits;
+    const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
+    const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
+    const uint64_t w0 = R >> 5;
+    for (uint32_t i = tid; i < nw; i += kEncThreads) {
+      if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
+      else cap = true;
+      S.words[i] = 0;
+    }
+    __syncthreads();
+    if (tid == 0 && !final_tile) {
+      // the partial last word becomes word 0 of the next tile
+      const uint32_t carry = S.words[endb >> 5];
+      S.words[endb >> 5] = 0;
+      S.words[0] = carry;
+    }
+    R += tile_bits;
+    if (t0 + kEncTile >= seg1) break;
+  }
+  return cap;
+}
+
 __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
     const qlc_table* __restrict__ table, const uint32_t* __restrict__ seg_hist,
@@ -350,130 +519,10 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 
   const uint64_t seg0 = (uint64_t)seg << log2_seg;
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
-  const bool last_seg = (seg == nseg - 1);
   bool cap = false;
   if (!bad_table) {
-    // ---- last bits of the previous segment (recomputed from its input) ----
-    if ((G & 31) != 0 && tid == 0) {
-      uint64_t acc = 0;
-      for (int k = 16; k >= 1; --k) {
-        const uint32_t e = S.lut[in[seg0 - k]];
-        acc = (acc << (e >> 11)) | (e & 0x7FFu);
-      }
-      S.words[0] = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
-    }
-    uint64_t R = G;  // global bit offset of the current tile
-    const uint64_t cmask = (1ull << log2_chunk) - 1;
-    uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
-    if (seg0 + kEncTile <= seg1) {
-      const uint4* p = reinterpret_cast<const uint4*>(in + seg0 + (uint64_t)tid * 16);
-      nx0 = p[0];
-      nx1 = p[kEncThreads];
-    }
-    for (uint64_t t0 = seg0;; t0 += kEncTile) {
-      const bool full = t0 + kEncTile <= seg1;
-      uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (full tiles)
-      uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
-      if (full) {
-        const uint4 v0 = nx0, v1 = nx1;
-        if (t0 + 2 * kEncTile <= seg1) {  // prefetch the next tile
-          const uint4* p = reinterpret_cast<const uint4*>(in + t0 + kEncTile + (uint64_t)tid * 16);
-          nx0 = p[0];
-          nx1 = p[kEncThreads];
-        }
-        const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const uint32_t w = sw[k >> 1];
-          const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
-          const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
-          const uint32_t l1 = e1 >> 11;
-          pc[k] = ((e0 & 0x7FFu) << l1) | (e1 & 0x7FFu);
-          pl[k] = (e0 >> 11) + l1;
-          if (k < 8) b0 += pl[k];
-          else b1 += pl[k];
-        }
-      } else {
-        // the input's ragged last tile: symbols [t0, seg1)
-#pragma unroll 1
-        for (int k = 0; k < 32; ++k) {
-          const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-          const uint32_t l = i < seg1 ? ((uint32_t)S.lut[in[i]] >> 11) : 0u;
-          if (k < 16) b0 += l;
-          else b1 += l;
-        }
-      }
-      // Thread tid owns two runs of the tile: symbols 16*tid.. (first half)
-      // and 4096+16*tid.. (second half), so that its loads are coalesced.
-      // Every first-half run precedes every second-half run in the stream;
-      // one block scan of the packed pair (b0 | b1 << 16) places both
-      // (run bits <= 176, block totals < 2^16).
-      const uint32_t packed = b0 | (b1 << 16);
-      const uint32_t incl = wave_inclusive_scan_u32(packed);
-      if (lane == 63) S.wave_sum[wave] = incl;
-      __syncthreads();
-      uint32_t o = 0, h = 0;
-#pragma unroll
-      for (int w = 0; w < kEncThreads / 64; ++w) {
-        const uint32_t ws = S.wave_sum[w];
-        o += (w < (int)wave) ? ws : 0u;
-        h += ws;
-      }
-      const uint32_t h0 = h & 0xFFFFu, h1 = h >> 16;
-      const uint32_t tile_bits = h0 + h1;
-      const uint32_t g = (uint32_t)(R & 31);
-      const uint32_t off0 = (o & 0xFFFFu) + (incl & 0xFFFFu) - b0;
-      const uint32_t off1 = h0 + (o >> 16) + (incl >> 16) - b1;
-      {
-        Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
-        Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
-        if (full) {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
-#pragma unroll
-          for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
-        } else {
-#pragma unroll 1
-          for (int k = 0; k < 32; ++k) {
-            const uint64_t i =
-                t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-            if (i < seg1) {
-              const uint32_t e = S.lut[in[i]];
-              if (k < 16) P0.put(S.words, e & 0x7FFu, e >> 11);
-              else P1.put(S.words, e & 0x7FFu, e >> 11);
-            }
-          }
-        }
-        P0.finish(S.words);
-        P1.finish(S.words);
-        // chunk index entries: a run's first symbol may start a chunk
-        const uint64_t i0s = t0 + (uint64_t)tid * 16;
-        const uint64_t i1s = i0s + kEncTile / 2;
-        if (i0s < seg1 && (i0s & cmask) == 0) index_out[i0s >> log2_chunk] = R + off0;
-        if (i1s < seg1 && (i1s & cmask) == 0) index_out[i1s >> log2_chunk] = R + off1;
-      }
-      __syncthreads();
-      // store the whole words (and, at the very end, the padded last word),
-      // clearing them for the next tile
-      const uint32_t endb = g + tile_bits;
-      const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
-      const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
-      const uint64_t w0 = R >> 5;
-      for (uint32_t i = tid; i < nw; i += kEncThreads) {
-        if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
-        else cap = true;
-        S.words[i] = 0;
-      }
-      __syncthreads();
-      if (tid == 0 && !final_tile) {
-        // the partial last word becomes word 0 of the next tile
-        const uint32_t carry = S.words[endb >> 5];
-        S.words[endb >> 5] = 0;
-        S.words[0] = carry;
-      }
-      R += tile_bits;
-      if (t0 + kEncTile >= seg1) break;
-    }
+    cap = encode_segment(in, seg0, seg1, G, seg == nseg - 1, log2_chunk, bits_out, cap_words,
+                         index_out, S, tid);
   } else if (tid == 0) {
     set_error(&hdr->enc_err, QLC_ERR_INVALID_ARGUMENT);
   }
@@ -597,18 +646,13 @@ __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __rest
   return r;
 }
 
-__global__ __launch_bounds__(kDecThreads) void k_decode(
-    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
-    const uint64_t* __restrict__ index, uint32_t log2_chunk,
-    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out,
-    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
-  __shared__ DecSmem S;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63;
-  const uint64_t total = *total_p;
-
-  // ---- code -> symbol LUT and the per-area shift table ----
-  uint32_t sh_lo = 0, sh_hi = 0;  // byte a = 29 - width[a]
+// Code -> symbol LUT of `table` into `lut` (2048 entries, bit 15 = invalid
+// suffix) and the per-area shift table (byte a of sh_hi:sh_lo = 29 - width).
+// Any block size; the caller synchronises before using the LUT.
+__device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint16_t* lut,
+                              uint32_t& sh_lo, uint32_t& sh_hi) {
+  sh_lo = 0;
+  sh_hi = 0;
   {
     uint32_t w[8], lo[8], off[8], first[8], cnt[8];
 #pragma unroll
@@ -621,7 +665,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
       if (a < 4) sh_lo |= (29u - w[a]) << (8 * a);
       else sh_hi |= (29u - w[a]) << (8 * (a - 4));
     }
-    for (uint32_t c = tid; c < 2048; c += kDecThreads) {
+    for (uint32_t c = threadIdx.x; c < 2048; c += blockDim.x) {
       uint16_t e = 0x8000;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
@@ -631,15 +675,25 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
             e = table->rank_to_sym[rank];
         }
       }
-      S.lut[c] = e;
+      lut[c] = e;
     }
   }
-  __syncthreads();
+}
 
+// Decode chunk group `grp` (chunks 128*grp .. 128*grp+127, one per lane;
+// tid = threadIdx.x)
+// of an n-symbol stream; S.lut holds the code -> symbol LUT.  Returns true
+// in a lane whose chunk is corrupt (or whose index entries are
+// inconsistent).
+__device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, uint64_t total,
+                             const uint64_t* __restrict__ index, uint32_t log2_chunk, uint64_t n,
+                             uint8_t* __restrict__ out, uint64_t grp, uint32_t sh_lo,
+                             uint32_t sh_hi, DecSmem& S, uint32_t tid) {
+  const uint32_t lane = tid & 63;
   const uint32_t C = 1u << log2_chunk;
   const uint64_t nchunks = (n + C - 1) >> log2_chunk;
-  const uint64_t j = (uint64_t)blockIdx.x * kDecThreads + tid;
-  const uint64_t j_wave = (uint64_t)blockIdx.x * kDecThreads +
+  const uint64_t j = grp * kDecThreads + tid;
+  const uint64_t j_wave = grp * kDecThreads +
                           (uint64_t)(__builtin_amdgcn_readfirstlane(tid) & ~63u);
   bool bad = false;
 
@@ -774,7 +828,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
           const uint32_t part = lane & 7u;                      // 8-byte piece of the run
           const uint32_t stid = (tid & ~63u) | src;
           const uint2 v = S.stage[stid * 8 + ((part ^ (stid >> 2)) & 7u)];
-          const uint64_t jj = (uint64_t)blockIdx.x * kDecThreads + stid;
+          const uint64_t jj = grp * kDecThreads + stid;
           const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
           if (g + part < ngrp)
             *reinterpret_cast<uint2*>(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8) = v;
@@ -808,6 +862,21 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
     }
     if (live) bad = (L.errbits & 0x8000u) || (L.pm1 + 1 != end);
   }
+  return bad;
+}
+
+__global__ __launch_bounds__(kDecThreads) void k_decode(
+    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
+    const uint64_t* __restrict__ index, uint32_t log2_chunk,
+    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out,
+    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
+  __shared__ DecSmem S;
+  const uint32_t tid = threadIdx.x;
+  uint32_t sh_lo, sh_hi;
+  build_dec_lut(table, S.lut, sh_lo, sh_hi);
+  __syncthreads();
+  const bool bad = decode_block(bits, *total_p, index, log2_chunk, n, out, blockIdx.x, sh_lo,
+                                sh_hi, S, tid);
 
   // ---- error word: first error wins; the last workgroup publishes it ----
   if (bad) set_error(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM);
@@ -819,6 +888,290 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
       store_relaxed_u32(&hdr->dec_err, 0);
       store_relaxed_u32(&hdr->dec_done, 0);
     }
+  }
+}
+
+// ===========================================================================
+// Batched form: many jobs of uneven sizes per launch.
+//
+// A one-workgroup plan kernel numbers the jobs' work units (encode
+// segments of 2^log2_seg symbols, or decode groups of 128 chunks), records
+// which job owns each unit and resets the per-call state.  The persistent
+// kernels then hand out work items from one atomic ticket counter.
+//
+// Encode items are, per segment g (all jobs' segments numbered jointly), a
+// histogram item H(g) and an encode item E(g).  The ticket order puts the
+// first `lag` histogram items first, then alternates E(0), H(lag),
+// E(1), H(lag + 1), ..., then the remaining encode items.  With lag at
+// least the largest job's segment count, every item an encode item waits
+// for (its job's histograms and table, the preceding segments' bit counts)
+// has a smaller ticket, so it was taken by a workgroup that is running and
+// that waits only on smaller tickets: no deadlock, whatever the grid size.
+// ===========================================================================
+// threadIdx.x, hidden from loop-invariant code motion: inside the
+// persistent loops, values derived from it are recomputed per item instead
+// of being held in registers across the whole loop.
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+__device__ __forceinline__ bool ptr_aligned(const void* p, uintptr_t a) {
+  return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
+}
+
+__device__ bool job_valid(const qlc_job& jb, bool decode) {
+  if (jb.n >= QLC_MAX_SYMBOLS_PER_CALL || jb.reserved != 0) return false;
+  if (!jb.table || !ptr_aligned(jb.table, 16) || !jb.total_bits || !ptr_aligned(jb.total_bits, 8))
+    return false;
+  if (!ptr_aligned(jb.chunk_index, 8) || !ptr_aligned(jb.bits, 16)) return false;
+  if (decode) {
+    if (jb.n && (!jb.bits || !jb.chunk_index || !jb.out || !ptr_aligned(jb.out, 16))) return false;
+  } else {
+    if (jb.n && (!jb.in || !ptr_aligned(jb.in, 16) || !jb.chunk_index)) return false;
+    if (jb.bits_capacity && !jb.bits) return false;
+  }
+  return true;
+}
+
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
+    const qlc_job* __restrict__ jobs, uint32_t n_jobs, uint32_t decode, uint32_t log2_unit,
+    uint64_t max_units, uint32_t lag_req, BatchHeader* __restrict__ hdr,
+    BatchJobState* __restrict__ js, uint32_t* __restrict__ unit_job,
+    uint64_t* __restrict__ seg_word) {
+  __shared__ uint64_t wsum[kPlanThreads / 64];
+  __shared__ uint32_t wmax[kPlanThreads / 64];
+  __shared__ uint64_t total_s;
+  __shared__ uint32_t maxc_s;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t per = (n_jobs + kPlanThreads - 1) / kPlanThreads;
+  const uint32_t k0 = tid * per < n_jobs ? tid * per : n_jobs;
+  const uint32_t k1 = k0 + per < n_jobs ? k0 + per : n_jobs;
+
+  // ---- units per job; per-job status reset ----
+  uint64_t local = 0;
+  uint32_t maxc = 0;
+  for (uint32_t k = k0; k < k1; ++k) {
+    const qlc_job jb = jobs[k];
+    uint32_t cnt = 0;
+    if (jb.err && ptr_aligned(jb.err, 4)) {
+      if (job_valid(jb, decode != 0)) {
+        const uint64_t u = (jb.n + (1ull << log2_unit) - 1) >> log2_unit;
+        cnt = (uint32_t)(decode ? u : (u ? u : 1));
+        *jb.err = 0;
+      } else {
+        *jb.err = QLC_ERR_INVALID_ARGUMENT;
+      }
+    }
+    js[k].count = cnt;
+    js[k].hist_done = 0;
+    js[k].table_ready = 0;
+    local += cnt;
+    maxc = cnt > maxc ? cnt : maxc;
+  }
+
+  // ---- exclusive scan of the unit counts over the jobs ----
+  const uint64_t incl = wave_inclusive_scan_u64(local);
+  uint32_t m = maxc;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint32_t o = __shfl_xor(m, d, 64);
+    m = o > m ? o : m;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  if (lane == 0) wmax[wave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t t = 0;
+    uint32_t mm = 0;
+    for (int w = 0; w < kPlanThreads / 64; ++w) {
+      const uint64_t v = wsum[w];
+      wsum[w] = t;
+      t += v;
+      mm = wmax[w] > mm ? wmax[w] : mm;
+    }
+    total_s = t;
+    maxc_s = mm;
+  }
+  __syncthreads();
+  const uint64_t total = total_s;
+  if (total > max_units) {
+    // workspace too small for these jobs: every job fails, nothing runs
+    for (uint32_t k = k0; k < k1; ++k) {
+      const qlc_job jb = jobs[k];
+      if (jb.err && ptr_aligned(jb.err, 4)) *jb.err = QLC_ERR_INVALID_ARGUMENT;
+      js[k].count = 0;
+    }
+    if (tid == 0) {
+      hdr->ticket = 0;
+      hdr->units = 0;
+      hdr->lag = 0;
+      hdr->abort = 1;
+    }
+    return;
+  }
+  uint64_t base = wsum[wave] + incl - local;
+  for (uint32_t k = k0; k < k1; ++k) {
+    const uint32_t cnt = js[k].count;
+    js[k].base = (uint32_t)base;
+    for (uint32_t u = 0; u < cnt; ++u) unit_job[base + u] = k;
+    base += cnt;
+  }
+  if (!decode)
+    for (uint64_t u = tid; u < total; u += kPlanThreads) seg_word[u] = 0;
+  if (tid == 0) {
+    uint64_t lag = lag_req == 0 ? total : (lag_req > maxc_s ? lag_req : maxc_s);
+    hdr->ticket = 0;
+    hdr->units = (uint32_t)total;
+    hdr->lag = (uint32_t)(lag < total ? lag : total);
+    hdr->abort = 0;
+  }
+}
+
+// Ticket p of the encode queue -> (histogram item?, segment).
+__device__ __forceinline__ bool encode_item(uint32_t p, uint32_t G, uint32_t L, uint32_t& g) {
+  if (p < L) {
+    g = p;
+    return true;
+  }
+  if (p < 2 * G - L) {
+    const uint32_t q = p - L;
+    g = (q & 1u) ? L + (q >> 1) : (q >> 1);
+    return (q & 1u) != 0;
+  }
+  g = p - G;
+  return false;
+}
+
+union BatchEncSmem {
+  uint32_t sub[256 * kHistCopies];
+  TableSmem table;
+  EncSmem enc;
+};
+
+__global__ __launch_bounds__(kEncThreads) void k_encode_batched(
+    const qlc_job* __restrict__ jobs, uint32_t mode, uint32_t log2_seg, uint32_t log2_chunk,
+    BatchHeader* __restrict__ hdr, BatchJobState* __restrict__ js,
+    uint64_t* __restrict__ job_hist, const uint32_t* __restrict__ seg_job,
+    uint64_t* __restrict__ seg_word, uint32_t* __restrict__ seg_hist) {
+  __shared__ BatchEncSmem S;
+  __shared__ uint32_t s_ticket, s_flag;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t G = hdr->units;
+  const uint32_t L = hdr->lag;
+  for (;;) {
+    if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
+    __syncthreads();
+    const uint32_t p = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (p >= 2 * G) break;
+    uint32_t g;
+    const bool hist = encode_item(p, G, L, g);
+    const uint32_t k = __builtin_amdgcn_readfirstlane(seg_job[g]);
+    const uint32_t base = js[k].base, cnt = js[k].count;
+    const qlc_job jb = jobs[k];
+    const uint32_t s = g - base;
+    const uint64_t seg0 = (uint64_t)s << log2_seg;
+    const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < jb.n ? seg0 + (1ull << log2_seg) : jb.n;
+
+    if (hist) {
+      // ---- H(g): the segment's histogram; the job's last one builds the table ----
+      for (uint32_t i = tid; i < 256 * kHistCopies; i += kEncThreads) S.sub[i] = 0;
+      __syncthreads();
+      hist_segment(jb.in, seg0, seg1, S.sub, opaque_tid());
+      __syncthreads();
+      const uint32_t v = hist_bin_total(S.sub, tid);
+      store_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid], v);
+      if (jb.build_table && v)
+        __hip_atomic_fetch_add(&job_hist[(uint64_t)k * 256 + tid], (uint64_t)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) s_flag = (atomic_add_u32(&js[k].hist_done, 1u) == cnt - 1);
+      __syncthreads();
+      if (s_flag) {
+        if (jb.build_table) {
+          S.table.h[tid] = load_relaxed_u64(&job_hist[(uint64_t)k * 256 + tid]);
+          store_relaxed_u64(&job_hist[(uint64_t)k * 256 + tid], 0);  // ready for the next call
+          build_table_block<true>(S.table.h, mode, jb.table, S.table);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+        }
+        if (tid == 0) store_relaxed_u32(&js[k].table_ready, 1u);
+      }
+    } else {
+      // ---- E(g): wait for the job's table, then encode the segment ----
+      if (tid == 0) {
+        while (load_relaxed_u32(&js[k].table_ready) == 0) __builtin_amdgcn_s_sleep(2);
+        S.enc.bad_table = 0;
+        S.enc.cap_hit = 0;
+      }
+      for (uint32_t w = tid; w < sizeof(S.enc.words) / 4; w += kEncThreads) S.enc.words[w] = 0;
+      __syncthreads();
+      if (tid < 128) {
+        const uint32_t* tw = reinterpret_cast<const uint32_t*>(jb.table);
+        const uint32_t w = load_relaxed_u32(&tw[tid]);
+        S.enc.lut[2 * tid] = (uint16_t)w;
+        S.enc.lut[2 * tid + 1] = (uint16_t)(w >> 16);
+      }
+      __syncthreads();
+      const uint32_t e_t = S.enc.lut[tid];
+      if ((e_t >> 11) < 3 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
+      const uint64_t my_bits = block_sum_u64(
+          (uint64_t)load_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid]) * (e_t >> 11), S.enc.red);
+      const bool bad_table = S.enc.bad_table != 0;
+      if (tid == 0) store_relaxed_u64(&seg_word[g], (1ull << 63) | my_bits);
+      uint64_t pre = 0;
+      for (uint32_t i = base + tid; i < g; i += kEncThreads) {
+        uint64_t w;
+        while (((w = load_relaxed_u64(&seg_word[i])) >> 63) == 0) __builtin_amdgcn_s_sleep(1);
+        pre += w & ~(1ull << 63);
+      }
+      const uint64_t G0 = block_sum_u64(pre, S.enc.red);
+      const bool last_seg = (s == cnt - 1);
+      if (last_seg && tid == 0) *jb.total_bits = G0 + my_bits;
+      bool cap = false;
+      if (!bad_table)
+        cap = encode_segment(jb.in, seg0, seg1, G0, last_seg, log2_chunk,
+                             reinterpret_cast<uint32_t*>(jb.bits), jb.bits_capacity / 4,
+                             jb.chunk_index, S.enc, opaque_tid());
+      if (cap) S.enc.cap_hit = 1;
+      __syncthreads();
+      if (tid == 0) {
+        if (bad_table) set_error(jb.err, QLC_ERR_INVALID_ARGUMENT);
+        else if (S.enc.cap_hit) set_error(jb.err, QLC_ERR_CAPACITY);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kDecThreads) void k_decode_batched(
+    const qlc_job* __restrict__ jobs, uint32_t log2_chunk, BatchHeader* __restrict__ hdr,
+    const BatchJobState* __restrict__ js, const uint32_t* __restrict__ grp_job) {
+  __shared__ DecSmem S;
+  __shared__ uint32_t s_ticket;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t units = hdr->units;
+  uint32_t cur = ~0u, sh_lo = 0, sh_hi = 0;
+  for (;;) {
+    if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
+    __syncthreads();
+    const uint32_t p = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (p >= units) break;
+    const uint32_t k = __builtin_amdgcn_readfirstlane(grp_job[p]);
+    const qlc_job jb = jobs[k];
+    if (k != cur) {
+      build_dec_lut(jb.table, S.lut, sh_lo, sh_hi);
+      __syncthreads();
+      cur = k;
+    }
+    const bool bad = decode_block(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk, jb.n,
+                                  jb.out, p - js[k].base, sh_lo, sh_hi, S, opaque_tid());
+    if (bad) set_error(jb.err, QLC_ERR_CORRUPT_STREAM);
+    __syncthreads();
   }
 }
 
@@ -873,6 +1226,40 @@ hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint6
   hipLaunchKernelGGL(k_decode, dim3((uint32_t)blocks), dim3(kDecThreads), 0, stream, bits, total,
                      index, log2_chunk, table, n, out, err_out, hdr);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
+                             uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
+                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, stream, jobs, n_jobs,
+                     decode ? 1u : 0u, log2_unit, max_units, lag, hdr, js, unit_job, seg_word);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t mode, uint32_t log2_seg,
+                                 uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
+                                 uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,
+                                 uint32_t* seg_hist, uint32_t grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_encode_batched, dim3(grid), dim3(kEncThreads), 0, stream, jobs, mode,
+                     log2_seg, log2_chunk, hdr, js, job_hist, seg_job, seg_word, seg_hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_batched(const qlc_job* jobs, uint32_t log2_chunk, BatchHeader* hdr,
+                                 const BatchJobState* js, const uint32_t* grp_job, uint32_t grid,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_decode_batched, dim3(grid), dim3(kDecThreads), 0, stream, jobs, log2_chunk,
+                     hdr, js, grp_job);
+  return hipGetLastError();
+}
+
+int batched_blocks_per_cu(bool decode) {
+  int nb = 0;
+  hipError_t e = decode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, reinterpret_cast<const void*>(k_decode_batched), kDecThreads, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                              &nb, reinterpret_cast<const void*>(k_encode_batched), kEncThreads, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_zero(void* p, uint64_t bytes, hipStream_t stream) {

@@ -59,6 +59,37 @@ class _Table(ctypes.Structure):
 
 assert ctypes.sizeof(_Table) == TABLE_BYTES
 
+
+class Job(ctypes.Structure):
+    """qlc_job: one tensor of a batched call (device pointers)."""
+    _fields_ = [
+        ("in_", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("table", ctypes.c_void_p),
+        ("bits", ctypes.c_void_p),
+        ("bits_capacity", ctypes.c_uint64),
+        ("chunk_index", ctypes.c_void_p),
+        ("total_bits", ctypes.c_void_p),
+        ("err", ctypes.c_void_p),
+        ("build_table", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+JOB_BYTES = 80
+assert ctypes.sizeof(Job) == JOB_BYTES
+
+
+class BatchTuning(ctypes.Structure):
+    """qlc_batch_tuning: work split of a batched call (0 = default)."""
+    _fields_ = [
+        ("log2_segment", ctypes.c_uint32),
+        ("lag_segments", ctypes.c_uint32),
+        ("workgroups", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
 _lib = None
 _vp = ctypes.c_void_p
 _u32 = ctypes.c_uint32
@@ -78,6 +109,9 @@ _SIGNATURES = {
     "qlc_compress": ([_vp, _u64, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp],
                      ctypes.c_int),
     "qlc_decode": ([_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_batched_workspace_bytes": ([_u32, _u64, _u32, _vp], _sz),
+    "qlc_encode_batched": ([_vp, _u32, ctypes.c_int, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_decode_batched": ([_vp, _u32, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_table_serialize": ([_vp, _vp], ctypes.c_int),
     "qlc_table_deserialize": ([_vp, _vp], ctypes.c_int),
 }
@@ -187,6 +221,35 @@ def qlc_decode(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor, chu
                             _p(err_out), _p(ws), _nbytes(ws), _stream(stream)), "qlc_decode")
 
 
+def _tuning_ptr(tuning):
+    if tuning is None:
+        return None, 0
+    if not isinstance(tuning, BatchTuning):
+        tuning = BatchTuning(*tuning)
+    return tuning, ctypes.addressof(tuning)
+
+
+def qlc_batched_workspace_bytes(n_jobs: int, total_symbols: int, chunk_symbols: int,
+                                tuning=None) -> int:
+    keep, tp = _tuning_ptr(tuning)
+    return int(lib().qlc_batched_workspace_bytes(n_jobs, total_symbols, chunk_symbols, tp))
+
+
+def qlc_encode_batched(jobs: torch.Tensor, n_jobs: int, mode: int, chunk_symbols: int,
+                       ws: torch.Tensor, tuning=None, stream=None):
+    """jobs: device tensor holding n_jobs qlc_job records."""
+    keep, tp = _tuning_ptr(tuning)
+    _check(lib().qlc_encode_batched(_p(jobs), n_jobs, mode, chunk_symbols, tp, _p(ws), _nbytes(ws),
+                                    _stream(stream)), "qlc_encode_batched")
+
+
+def qlc_decode_batched(jobs: torch.Tensor, n_jobs: int, chunk_symbols: int, ws: torch.Tensor,
+                       tuning=None, stream=None):
+    keep, tp = _tuning_ptr(tuning)
+    _check(lib().qlc_decode_batched(_p(jobs), n_jobs, chunk_symbols, tp, _p(ws), _nbytes(ws),
+                                    _stream(stream)), "qlc_decode_batched")
+
+
 def qlc_table_serialize(table_host: bytes | np.ndarray) -> bytes:
     t = np.frombuffer(bytes(table_host), dtype=np.uint8).copy()
     out = np.zeros(SERIALIZED_TABLE_BYTES, dtype=np.uint8)
@@ -268,3 +331,99 @@ def decompress(c: Compressed, out: torch.Tensor | None = None, ws: torch.Tensor 
     ws = new_workspace(0, c.chunk_symbols, dev) if ws is None else ws
     qlc_decode(c.bits, c.total, c.index, c.chunk_symbols, c.table, c.n, out, err, ws)
     return out, err
+
+
+# ------------------------------------------------------------ batches
+def _align(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
+class Batch:
+    """Device buffers of a batch of tensors, carved from a few pooled
+    allocations (256-byte aligned slices), and the device array of qlc_job
+    records that points into them.
+
+    capacity: "search" (n + 16 bytes of bitstream per tensor: enough for any
+    table a SEARCH mode builds from the tensor's own histogram, whose cost
+    never exceeds 8 bits per symbol) or "bound" (qlc_encode_bound_bytes).
+    """
+
+    def __init__(self, sizes, chunk_symbols: int = 4096, device="cuda", capacity="search",
+                 build_table: bool = True):
+        self.sizes = [int(v) for v in sizes]
+        self.S = len(self.sizes)
+        self.C = chunk_symbols
+        self.device = torch.device(device)
+        self.in_off, self.bits_off, self.idx_off, self.cap = [], [], [], []
+        oi = ob = ox = 0
+        for n in self.sizes:
+            cap = _align(n + 16, 16) if capacity == "search" else qlc_encode_bound_bytes(n)
+            self.in_off.append(oi)
+            self.bits_off.append(ob)
+            self.idx_off.append(ox)
+            self.cap.append(cap)
+            oi += _align(max(n, 1))
+            ob += _align(max(cap, 16))
+            ox += _align(max(qlc_chunk_count(n, chunk_symbols), 1), 32)
+        dev = self.device
+        self.inp = torch.zeros(max(oi, 256), dtype=torch.uint8, device=dev)
+        self.out = torch.zeros(max(oi, 256), dtype=torch.uint8, device=dev)
+        self.bits = torch.zeros(max(ob, 256), dtype=torch.uint8, device=dev)
+        self.index = torch.zeros(max(ox, 32), dtype=torch.int64, device=dev)
+        self.tables = torch.zeros(self.S * TABLE_BYTES, dtype=torch.uint8, device=dev)
+        self.total = torch.zeros(self.S, dtype=torch.int64, device=dev)
+        self.err = torch.zeros(self.S, dtype=torch.int32, device=dev)
+        self.build_table = build_table
+        self.jobs_host = (Job * self.S)()
+        self._fill_jobs()
+        self.jobs = torch.frombuffer(bytearray(self.jobs_host), dtype=torch.uint8).to(dev)
+
+    def _fill_jobs(self):
+        for i, n in enumerate(self.sizes):
+            j = self.jobs_host[i]
+            j.in_ = self.inp.data_ptr() + self.in_off[i]
+            j.out = self.out.data_ptr() + self.in_off[i]
+            j.n = n
+            j.table = self.tables.data_ptr() + i * TABLE_BYTES
+            j.bits = self.bits.data_ptr() + self.bits_off[i]
+            j.bits_capacity = self.cap[i]
+            j.chunk_index = self.index.data_ptr() + 8 * self.idx_off[i]
+            j.total_bits = self.total.data_ptr() + 8 * i
+            j.err = self.err.data_ptr() + 4 * i
+            j.build_table = 1 if self.build_table else 0
+            j.reserved = 0
+
+    def upload_jobs(self):
+        """Copy the (edited) host job records to the device array."""
+        self.jobs.copy_(torch.frombuffer(bytearray(self.jobs_host), dtype=torch.uint8))
+
+    @property
+    def total_symbols(self) -> int:
+        return sum(self.sizes)
+
+    def workspace(self, tuning=None) -> torch.Tensor:
+        b = qlc_batched_workspace_bytes(self.S, self.total_symbols, self.C, tuning)
+        return torch.zeros(max(b, 256), dtype=torch.uint8, device=self.device)
+
+    def input(self, i: int) -> torch.Tensor:
+        return self.inp[self.in_off[i]:self.in_off[i] + self.sizes[i]]
+
+    def output(self, i: int) -> torch.Tensor:
+        return self.out[self.in_off[i]:self.in_off[i] + self.sizes[i]]
+
+    def table(self, i: int) -> torch.Tensor:
+        return self.tables[i * TABLE_BYTES:(i + 1) * TABLE_BYTES]
+
+    def bitstream(self, i: int, nbytes: int | None = None) -> torch.Tensor:
+        nb = self.cap[i] if nbytes is None else nbytes
+        return self.bits[self.bits_off[i]:self.bits_off[i] + nb]
+
+    def chunk_index(self, i: int) -> torch.Tensor:
+        k = qlc_chunk_count(self.sizes[i], self.C)
+        return self.index[self.idx_off[i]:self.idx_off[i] + k]
+
+    def encode(self, ws: torch.Tensor, mode: int = LAYOUT_SEARCH_QUAD, tuning=None, stream=None):
+        qlc_encode_batched(self.jobs, self.S, mode, self.C, ws, tuning, stream)
+
+    def decode(self, ws: torch.Tensor, tuning=None, stream=None):
+        qlc_decode_batched(self.jobs, self.S, self.C, ws, tuning, stream)
