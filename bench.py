@@ -10,7 +10,11 @@ workload is the single 256 MiB e4m3 tensor (8192 x 32768, Laplace(0,1) with
 
 Prints one JSON line.  `value` is uncompressed bytes per second of a whole
 step (N / (t_compress + t_decode)); per-kernel rates, the roofline of the
-dominant kernel and the CPU oracle baseline ride along.
+dominant kernel and the CPU oracle baseline ride along.  The `batched`
+object reports the batched form on 1152 uneven shards (one persistent
+encode launch and one persistent decode launch, each replayed from a
+hipGraph, work split from the autotuner) against plain per-shard launches
+of the single-tensor entry points, with the outputs compared byte for byte.
 """
 from __future__ import annotations
 
@@ -83,6 +87,111 @@ def cpu_baseline(x_host, chunk, budget_s=20.0):
                       "histogram+table+encode+decode, %.1f s" % (xs.size, reps, el)}
 
 
+BATCH_WORKLOAD = ("1152 shards (18 x 64), sizes log-uniform in 1-32 MiB, multiples of 32 B "
+                  "(seed 2); shard i: N(0,1) activations, Student-t(3) gradients or N(0,0.02) "
+                  "weights by i mod 3, block-32 e4m3; per-shard SEARCH_QUAD table")
+
+
+def run_batched(dev, steps, plain_steps=2):
+    """Batched form vs plain per-shard launches on the 1152-shard workload."""
+    import torch
+
+    from paper_2602_17849_amd import autotune, datagen, qlc
+
+    mode = qlc.LAYOUT_SEARCH_QUAD
+    sizes = datagen.shard_sizes()
+    S, total = len(sizes), sum(sizes)
+    cmin = min(autotune.CHUNKS)
+    A = qlc.Batch(sizes, chunk_symbols=cmin, device=dev, min_chunk=cmin)
+    for i, n in enumerate(sizes):
+        A.input(i).copy_(datagen.shard(i, n, device=dev))
+    torch.cuda.synchronize()
+    print("batched: %d shards, %.2f GiB generated" % (S, total / 2**30), file=sys.stderr,
+          flush=True)
+
+    ch = autotune.tune_batched(A, mode)
+    C = ch.chunk_symbols
+    A.set_chunk(C)
+    A.index.zero_()  # drop the entries other chunk sizes left while tuning
+    tuning = ch.tuning()
+    ws = A.workspace(tuning)
+    stream = torch.cuda.current_stream()
+
+    g_enc, g_dec = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_enc):
+        A.encode(ws, mode, tuning)
+    with torch.cuda.graph(g_dec):
+        A.decode(ws, tuning)
+    for _ in range(2):
+        g_enc.replay()
+        g_dec.replay()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        evs[k][0].record(stream)
+        g_enc.replay()
+        evs[k][1].record(stream)
+        g_dec.replay()
+        evs[k][2].record(stream)
+    torch.cuda.synchronize()
+    t_enc = sum(e[0].elapsed_time(e[1]) for e in evs) / steps / 1e3
+    t_dec = sum(e[1].elapsed_time(e[2]) for e in evs) / steps / 1e3
+    assert not A.err.any().item(), "batched call reported an error"
+    assert torch.equal(A.out, A.inp), "batched round trip mismatch"
+
+    # plain per-shard launches of the single-tensor entry points, same C
+    B = qlc.Batch(sizes, chunk_symbols=C, device=dev, min_chunk=cmin, inp=A.inp)
+    wsp = torch.zeros(max(qlc.qlc_workspace_bytes(n, C) for n in sizes), dtype=torch.uint8,
+                      device=dev)
+    derr = torch.zeros(S, dtype=torch.int32, device=dev)
+    args = [(B.input(i), B.table(i), B.bitstream(i), B.chunk_index(i, whole=True),
+             B.total[i:i + 1], B.err[i:i + 1], B.output(i), derr[i:i + 1], n)
+            for i, n in enumerate(sizes)]
+
+    def plain_pass():
+        for x, t, bits, idx, tot, err, out, de, n in args:
+            qlc.qlc_compress(x, mode, t, C, bits, idx, tot, err, wsp)
+            qlc.qlc_decode(bits, tot, idx, C, t, n, out, de, wsp)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    t_plain = timed(plain_pass, plain_steps)
+    g_plain = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_plain):
+        plain_pass()
+    t_plain_graph = timed(g_plain.replay, plain_steps)
+    assert not B.err.any().item() and not derr.any().item()
+    same = {"bits": torch.equal(A.bits, B.bits), "index": torch.equal(A.index, B.index),
+            "tables": torch.equal(A.tables, B.tables), "total": torch.equal(A.total, B.total),
+            "plain_round_trip": torch.equal(B.out, A.inp)}
+    exact = all(same.values())
+    assert exact, "batched and plain outputs differ: %s" % same
+    t_b = t_enc + t_dec
+    return {
+        "workload": BATCH_WORKLOAD, "shards": S, "symbols": total, "chunk_symbols": C,
+        "log2_segment": ch.log2_segment, "lag_segments": ch.lag_segments,
+        "form": "qlc_encode_batched + qlc_decode_batched, each one hipGraph replay",
+        "gbps": round(total / t_b / 1e9, 2),
+        "encode_gbps": round(total / t_enc / 1e9, 2),
+        "decode_gbps": round(total / t_dec / 1e9, 2),
+        "plain_per_shard_gbps": round(total / t_plain / 1e9, 2),
+        "plain_per_shard_graph_gbps": round(total / t_plain_graph / 1e9, 2),
+        "speedup_vs_plain": round(t_plain / t_b, 3),
+        "speedup_vs_plain_graph": round(t_plain_graph / t_b, 3),
+        "bit_exact_vs_plain": bool(exact),
+        "stream_bytes": int(((A.total + 31) // 32 * 4).sum().item()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +199,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--chunk", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,8 +308,13 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": dec_bytes},
     }
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(x.cpu().numpy(), C)
+    x_host = None if args.no_cpu_baseline else x.cpu().numpy()
+    if not args.no_batched:
+        del x, out, bits, ws
+        torch.cuda.empty_cache()
+        res["batched"] = run_batched(dev, max(3, min(args.steps, 10)))
+    if x_host is not None:
+        res["cpu_baseline"] = cpu_baseline(x_host, C)
     print(json.dumps(res), flush=True)
 
 

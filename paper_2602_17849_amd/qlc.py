@@ -349,10 +349,13 @@ class Batch:
     """
 
     def __init__(self, sizes, chunk_symbols: int = 4096, device="cuda", capacity="search",
-                 build_table: bool = True):
+                 build_table: bool = True, min_chunk: int | None = None,
+                 inp: torch.Tensor | None = None):
         self.sizes = [int(v) for v in sizes]
         self.S = len(self.sizes)
         self.C = chunk_symbols
+        # chunk indexes are sized for min_chunk, so any C >= min_chunk fits
+        self.min_chunk = chunk_symbols if min_chunk is None else min(min_chunk, chunk_symbols)
         self.device = torch.device(device)
         self.in_off, self.bits_off, self.idx_off, self.cap = [], [], [], []
         oi = ob = ox = 0
@@ -364,9 +367,13 @@ class Batch:
             self.cap.append(cap)
             oi += _align(max(n, 1))
             ob += _align(max(cap, 16))
-            ox += _align(max(qlc_chunk_count(n, chunk_symbols), 1), 32)
+            ox += _align(max(qlc_chunk_count(n, self.min_chunk), 1), 32)
         dev = self.device
-        self.inp = torch.zeros(max(oi, 256), dtype=torch.uint8, device=dev)
+        if inp is not None:
+            assert inp.dtype == torch.uint8 and inp.numel() >= oi and inp.data_ptr() % 256 == 0
+            self.inp = inp
+        else:
+            self.inp = torch.zeros(max(oi, 256), dtype=torch.uint8, device=dev)
         self.out = torch.zeros(max(oi, 256), dtype=torch.uint8, device=dev)
         self.bits = torch.zeros(max(ob, 256), dtype=torch.uint8, device=dev)
         self.index = torch.zeros(max(ox, 32), dtype=torch.int64, device=dev)
@@ -418,9 +425,14 @@ class Batch:
         nb = self.cap[i] if nbytes is None else nbytes
         return self.bits[self.bits_off[i]:self.bits_off[i] + nb]
 
-    def chunk_index(self, i: int) -> torch.Tensor:
-        k = qlc_chunk_count(self.sizes[i], self.C)
-        return self.index[self.idx_off[i]:self.idx_off[i] + k]
+    def chunk_index(self, i: int, whole: bool = False) -> torch.Tensor:
+        """Job i's index entries at the current C (whole: its whole slot)."""
+        k = qlc_chunk_count(self.sizes[i], self.min_chunk if whole else self.C)
+        return self.index[self.idx_off[i]:self.idx_off[i] + max(k, 1 if whole else 0)]
+
+    def set_chunk(self, chunk_symbols: int):
+        assert chunk_symbols >= self.min_chunk
+        self.C = chunk_symbols
 
     def encode(self, ws: torch.Tensor, mode: int = LAYOUT_SEARCH_QUAD, tuning=None, stream=None):
         qlc_encode_batched(self.jobs, self.S, mode, self.C, ws, tuning, stream)
