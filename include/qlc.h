@@ -209,9 +209,10 @@ typedef struct qlc_batch_tuning {
 } qlc_batch_tuning;
 
 /* Workspace bytes for batched calls over n_jobs jobs holding at most
- * total_symbols symbols together (h_tuning may be NULL).  The workspace is
- * zeroed once before first use (qlc_workspace_init) and must not be shared
- * with the single-tensor entry points without zeroing it again. */
+ * total_symbols symbols together (h_tuning may be NULL).  Every batched call
+ * resets the state it uses, so a batched workspace needs no zeroing; a
+ * workspace handed to the single-tensor entry points after batched calls
+ * must be zeroed (qlc_workspace_init) first. */
 size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols,
                                    uint32_t chunk_symbols,
                                    const qlc_batch_tuning* h_tuning);

@@ -277,7 +277,7 @@ qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_m
   if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
   BatchView v = carve_batch(ws, ws_bytes, n_jobs, false);
   hipError_t e = launch_batch_plan(jobs, n_jobs, false, log2_seg, v.max_units, lag, v.hdr, v.js,
-                                   v.unit_job, v.seg_word, stream);
+                                   v.job_hist, v.unit_job, v.seg_word, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
   return hip_status(launch_encode_batched(jobs, (uint32_t)mode, log2_seg, log2c, v.hdr, v.js,
                                           v.job_hist, v.unit_job, v.seg_word, v.seg_hist,
@@ -295,7 +295,7 @@ qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chu
   if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
   BatchView v = carve_batch(ws, ws_bytes, n_jobs, true);
   hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + 7, v.max_units, 0, v.hdr, v.js,
-                                   v.unit_job, nullptr, stream);
+                                   v.job_hist, v.unit_job, nullptr, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
   return hip_status(launch_decode_batched(jobs, log2c, v.hdr, v.js, v.unit_job,
                                           persistent_grid(true, wgs), stream));

@@ -21,7 +21,8 @@ hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint6
                          uint32_t* err_out, WsHeader* hdr, hipStream_t stream);
 hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
                              uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
-                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream);
+                             uint64_t* job_hist, uint32_t* unit_job, uint64_t* seg_word,
+                             hipStream_t stream);
 hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t mode, uint32_t log2_seg,
                                  uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
                                  uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,

@@ -936,12 +936,21 @@ __device__ bool job_valid(const qlc_job& jb, bool decode) {
 }
 
 constexpr int kPlanThreads = 1024;
+constexpr uint32_t kPlanZeroJobs = 16;  // job histograms cleared per extra plan workgroup
 
+// Workgroup 0 plans; workgroups 1.. (encode only) clear the per-job
+// histogram accumulators, kPlanZeroJobs jobs each.
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
     const qlc_job* __restrict__ jobs, uint32_t n_jobs, uint32_t decode, uint32_t log2_unit,
     uint64_t max_units, uint32_t lag_req, BatchHeader* __restrict__ hdr,
-    BatchJobState* __restrict__ js, uint32_t* __restrict__ unit_job,
-    uint64_t* __restrict__ seg_word) {
+    BatchJobState* __restrict__ js, uint64_t* __restrict__ job_hist,
+    uint32_t* __restrict__ unit_job, uint64_t* __restrict__ seg_word) {
+  if (blockIdx.x > 0) {
+    const uint64_t k0 = (uint64_t)(blockIdx.x - 1) * kPlanZeroJobs;
+    const uint64_t k1 = k0 + kPlanZeroJobs < n_jobs ? k0 + kPlanZeroJobs : n_jobs;
+    for (uint64_t i = k0 * 256 + threadIdx.x; i < k1 * 256; i += kPlanThreads) job_hist[i] = 0;
+    return;
+  }
   __shared__ uint64_t wsum[kPlanThreads / 64];
   __shared__ uint32_t wmax[kPlanThreads / 64];
   __shared__ uint64_t total_s;
@@ -1094,7 +1103,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode_batched(
       if (s_flag) {
         if (jb.build_table) {
           S.table.h[tid] = load_relaxed_u64(&job_hist[(uint64_t)k * 256 + tid]);
-          store_relaxed_u64(&job_hist[(uint64_t)k * 256 + tid], 0);  // ready for the next call
           build_table_block<true>(S.table.h, mode, jb.table, S.table);
           __builtin_amdgcn_s_waitcnt(0);
           __syncthreads();
@@ -1230,9 +1238,12 @@ hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint6
 
 hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
                              uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
-                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, stream, jobs, n_jobs,
-                     decode ? 1u : 0u, log2_unit, max_units, lag, hdr, js, unit_job, seg_word);
+                             uint64_t* job_hist, uint32_t* unit_job, uint64_t* seg_word,
+                             hipStream_t stream) {
+  const uint32_t grid = 1 + (decode ? 0u : (n_jobs + kPlanZeroJobs - 1) / kPlanZeroJobs);
+  hipLaunchKernelGGL(k_batch_plan, dim3(grid), dim3(kPlanThreads), 0, stream, jobs, n_jobs,
+                     decode ? 1u : 0u, log2_unit, max_units, lag, hdr, js, job_hist, unit_job,
+                     seg_word);
   return hipGetLastError();
 }
 

@@ -439,3 +439,140 @@ class Batch:
 
     def decode(self, ws: torch.Tensor, tuning=None, stream=None):
         qlc_decode_batched(self.jobs, self.S, self.C, ws, tuning, stream)
+
+
+# ------------------------------------------------------------ serving
+REQUEST_COMPRESS = 0
+REQUEST_DECOMPRESS = 1
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("memory_budget_bytes", ctypes.c_uint64), ("max_tick_symbols", ctypes.c_uint64),
+                ("chunk_symbols", ctypes.c_uint32), ("layout_mode", ctypes.c_uint32),
+                ("max_jobs_per_tick", ctypes.c_uint32), ("max_ticks_in_flight", ctypes.c_uint32),
+                ("log2_segment", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("in_", ctypes.c_void_p), ("table", ctypes.c_void_p), ("bits", ctypes.c_void_p),
+                ("chunk_index", ctypes.c_void_p), ("total_bits", ctypes.c_void_p),
+                ("user_tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("user_tag", ctypes.c_uint64), ("kind", ctypes.c_uint32),
+                ("status", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("total_bits", ctypes.c_uint64), ("table", ctypes.c_void_p),
+                ("bits", ctypes.c_void_p), ("chunk_index", ctypes.c_void_p),
+                ("total_bits_dev", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64),
+                ("complete_ns", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("peak_bytes_in_use", ctypes.c_uint64), ("submitted", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("ticks", ctypes.c_uint64), ("max_jobs_in_tick", ctypes.c_uint32),
+                ("max_ticks_in_flight", ctypes.c_uint32), ("queued", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(ServerConfig) == 40 and ctypes.sizeof(Request) == 64
+assert ctypes.sizeof(Result) == 104 and ctypes.sizeof(ServerStats) == 72
+
+_SIGNATURES.update({
+    "qlc_server_create": ([_vp, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qlc_server_submit": ([_vp, _vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "qlc_server_poll": ([_vp, _vp, _u32, ctypes.c_int64], _u32),
+    "qlc_server_release": ([_vp, _u64], ctypes.c_int),
+    "qlc_server_get_stats": ([_vp, _vp], ctypes.c_int),
+    "qlc_server_destroy": ([_vp], ctypes.c_int),
+})
+
+
+def device_copy(ptr: int, nbytes: int, device="cuda") -> torch.Tensor:
+    """A new uint8 tensor holding `nbytes` of device memory at `ptr` (server
+    results live in the server's pool); the copy runs on the current stream."""
+    out = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    if nbytes:
+        _hip_memcpy_d2d(out.data_ptr(), ptr, nbytes)
+    return out
+
+
+def _hip_memcpy_d2d(dst: int, src: int, nbytes: int):
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [_vp, _vp, _sz, ctypes.c_int, _vp]
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+    rc = _hip.hipMemcpyAsync(dst, src, nbytes, 3, _stream(None))  # device to device
+    if rc != 0:
+        raise QLCError(QLC_ERR_HIP, "hipMemcpyAsync")
+
+
+_hip = None
+
+
+class Server:
+    """The serving loop of libqlc (qlc_server_*): submit compress /
+    decompress requests, poll completions, release their outputs."""
+
+    def __init__(self, memory_budget_bytes: int, chunk_symbols: int = 4096,
+                 layout_mode: int = LAYOUT_SEARCH_QUAD, max_jobs_per_tick: int = 0,
+                 max_ticks_in_flight: int = 0, log2_segment: int = 0, max_tick_symbols: int = 0):
+        lib()
+        cfg = ServerConfig(memory_budget_bytes, max_tick_symbols, chunk_symbols, layout_mode,
+                           max_jobs_per_tick, max_ticks_in_flight, log2_segment, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.qlc_server_create(ctypes.addressof(cfg), ctypes.byref(h)), "qlc_server_create")
+        self._h = h
+        self.chunk_symbols = chunk_symbols
+
+    def submit_compress(self, x: torch.Tensor, table: torch.Tensor | None = None,
+                        user_tag: int = 0, n: int | None = None) -> int:
+        n = x.numel() if n is None else n
+        r = Request(REQUEST_COMPRESS, 0, n, _p(x), _p(table), 0, 0, 0, user_tag)
+        return self._submit(r)
+
+    def submit_decompress(self, n: int, bits, index, total, table, user_tag: int = 0) -> int:
+        r = Request(REQUEST_DECOMPRESS, 0, n, 0, _p(table), _p(bits), _p(index), _p(total),
+                    user_tag)
+        return self._submit(r)
+
+    def _submit(self, r: Request) -> int:
+        rid = ctypes.c_uint64()
+        _check(_lib.qlc_server_submit(self._h, ctypes.addressof(r), ctypes.byref(rid)),
+               "qlc_server_submit")
+        return int(rid.value)
+
+    def poll(self, max_results: int = 64, timeout_us: int = 0) -> list:
+        buf = (Result * max_results)()
+        k = _lib.qlc_server_poll(self._h, ctypes.addressof(buf), max_results, timeout_us)
+        return [buf[i] for i in range(k)]
+
+    def release(self, rid: int):
+        _check(_lib.qlc_server_release(self._h, rid), "qlc_server_release")
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(_lib.qlc_server_get_stats(self._h, ctypes.addressof(st)), "qlc_server_get_stats")
+        return st
+
+    def close(self):
+        if self._h:
+            _check(_lib.qlc_server_destroy(self._h), "qlc_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -265,3 +265,21 @@ def test_batched_graph_replay():
             for a, e in zip(r[2:], eager[i][2:]):
                 assert np.array_equal(a, e), i
         check_round_trip(b, xs)
+
+
+def test_batched_workspace_shared_by_batches_of_different_sizes():
+    """One workspace serves batches with different job counts in turn (the
+    per-call state sits at offsets that depend on the job count)."""
+    C = 1024
+    b1, xs1 = make_batch(SIZES, C, seed=11)
+    b2, xs2 = make_batch(SIZES[:3] + SIZES[9:11], C, seed=12)
+    b3, xs3 = make_batch(SIZES[5:6], C, seed=13)
+    wsb = max(b.workspace().numel() for b in (b1, b2, b3))
+    ws = torch.full((wsb,), 0xA5, dtype=torch.uint8, device=DEV)   # no zeroing needed
+    for b, xs in ((b1, xs1), (b2, xs2), (b3, xs3), (b1, xs1), (b3, xs3), (b2, xs2)):
+        b.bits.zero_()
+        b.encode(ws, 0)
+        b.decode(ws)
+        torch.cuda.synchronize()
+        check_against_oracle(b, xs, 0, C)
+        check_round_trip(b, xs)
