@@ -192,6 +192,89 @@ def run_batched(dev, steps, plain_steps=2):
     }
 
 
+SERVE_WORKLOAD = ("Poisson arrivals, mean 2000 req/s for 10 s (seed 3), 50/50 compress / "
+                  "decompress, sizes log-uniform 64 KiB-64 MiB (multiples of 32 B) of Laplace "
+                  "block-32 e4m3; compress inputs are slices of a resident 1 GiB tensor, "
+                  "decompress requests cycle over 256 objects pre-compressed at setup; "
+                  "32 GiB device budget")
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def run_serving(dev, duration_s=10.0, chunk=1024, log2_segment=16, budget=32 << 30):
+    """The serving loop (qlc_server_*) under Poisson arrivals, then the same
+    requests submitted at once (saturation)."""
+    import torch
+
+    from paper_2602_17849_amd import datagen, qlc
+
+    reqs = datagen.serving_requests(duration_s=duration_s, rate=2000.0, seed=3)
+    pool = datagen.laplace_outlier_rows(1024, 1 << 20, seed=30, device=dev)  # 1 GiB
+    pool_n = pool.numel()
+    dec_sizes = [n for _, k, n in reqs if k == "decompress"][:256]
+    objs = []
+    for j, n in enumerate(dec_sizes):
+        off = (j * 1_048_573 * 256) % (pool_n - n) // 256 * 256
+        objs.append(qlc.compress(pool[off:off + n], chunk_symbols=chunk))
+    torch.cuda.synchronize()
+    assert all(int(o.err.item()) == 0 for o in objs)
+    print("serving: %d requests, %d objects resident" % (len(reqs), len(objs)), file=sys.stderr,
+          flush=True)
+
+    def submit(srv, i, kind, n):
+        if kind == "compress":
+            off = (i * 2_654_435 * 256) % (pool_n - n) // 256 * 256
+            return srv.submit_compress(pool[off:off + n], n=n), n
+        o = objs[i % len(objs)]
+        return srv.submit_decompress(o.n, o.bits, o.index, o.total, o.table), o.n
+
+    def drain(srv, pending, lat, done_bytes, last):
+        for r in srv.poll(256, 0):
+            t_arr, nbytes = pending.pop(r.id)
+            if r.status != 0:
+                raise RuntimeError("serving request failed with status %d" % r.status)
+            lat.append((r.complete_ns - t_arr) / 1e3)
+            done_bytes[0] += nbytes
+            last[0] = max(last[0], r.complete_ns)
+            srv.release(r.id)
+
+    out = {}
+    for mode in ("poisson", "saturation"):
+        srv = qlc.Server(budget, chunk_symbols=chunk, max_jobs_per_tick=64,
+                         max_ticks_in_flight=4, log2_segment=log2_segment)
+        lat, done_bytes, last, pending = [], [0], [0], {}
+        t0 = time.perf_counter_ns()
+        for i, (t_arr, kind, n) in enumerate(reqs):
+            if mode == "poisson":
+                due = t0 + int(t_arr * 1e9)
+                while time.perf_counter_ns() < due:
+                    drain(srv, pending, lat, done_bytes, last)
+            else:
+                due = t0
+            rid, nbytes = submit(srv, i, kind, n)
+            pending[rid] = (due, nbytes)
+        while pending:
+            drain(srv, pending, lat, done_bytes, last)
+        st = srv.stats()
+        srv.close()
+        span = (last[0] - t0) / 1e9
+        out[mode] = {
+            "requests": len(reqs), "bytes": done_bytes[0],
+            "gbps": round(done_bytes[0] / span / 1e9, 2),
+            "p50_us": round(_pct(lat, 50), 1), "p99_us": round(_pct(lat, 99), 1),
+            "p999_us": round(_pct(lat, 99.9), 1), "makespan_s": round(span, 4),
+            "ticks": int(st.ticks), "max_jobs_in_tick": int(st.max_jobs_in_tick),
+            "max_ticks_in_flight": int(st.max_ticks_in_flight),
+            "peak_bytes_in_use": int(st.peak_bytes_in_use)}
+        print("serving %s: %s" % (mode, out[mode]), file=sys.stderr, flush=True)
+    return {"workload": SERVE_WORKLOAD, "chunk_symbols": chunk, "log2_segment": log2_segment,
+            "budget_bytes": budget, "latency": "scheduled arrival to completion seen by the "
+            "server thread", **out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +283,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -313,6 +398,10 @@ def main():
         del x, out, bits, ws
         torch.cuda.empty_cache()
         res["batched"] = run_batched(dev, max(3, min(args.steps, 10)))
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        res["serving"] = run_serving(dev, args.serve_seconds)
+        torch.cuda.empty_cache()
     if x_host is not None:
         res["cpu_baseline"] = cpu_baseline(x_host, C)
     print(json.dumps(res), flush=True)
