@@ -7,9 +7,11 @@ runs, on the GPU machine, from the repository root:
   2. rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, on bench.py;
   3. the same two counters on a plain 256 MiB device copy (torch copy_),
      whose true bytes are known, to scale the counters to bytes;
-and writes profiles/traffic.json (HBM bytes per launch of each libqlc
-kernel, tagged with the hash of the kernel sources) and
-profiles/kernels_single_tensor_256MiB.md (the summary, with the commands).
+and writes gpurun_out/bench_profile/traffic.json (HBM bytes per launch of
+each libqlc kernel, tagged with the hash of the kernel sources) and
+gpurun_out/bench_profile/kernels_single_tensor_256MiB.md (the summary, with
+the commands); both are then copied into profiles/, where bench.py reads
+traffic.json while the kernel sources still match its hash.
 
     python3 bench_profile.py copy     # the calibration workload itself
 """
@@ -77,7 +79,7 @@ def kernel_stats(d):
 def collect(chunk):
     os.makedirs(OUT, exist_ok=True)
     bench = ["python3", "bench.py", "--steps", "5", "--warmup", "2", "--no-cpu-baseline",
-             "--chunk", str(chunk)]
+             "--no-batched", "--no-serving", "--chunk", str(chunk)]
     cmds = {}
     cmds["trace"] = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv",
                      "-d", os.path.join(OUT, "trace"), "-o", "trace", "--"] + bench
@@ -121,8 +123,7 @@ def collect(chunk):
            "read_scale": scale_r, "write_scale": scale_w, "kernels": kernels,
            "commands": {k: " ".join(v) for k, v in cmds.items()},
            "date": time.strftime("%Y-%m-%d %H:%M:%S")}
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(os.path.join(OUT, "traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
 
     stats = kernel_stats(os.path.join(OUT, "trace"))
@@ -148,7 +149,7 @@ def collect(chunk):
             k, v["fetch_kb"], v["write_kb"], (v["read_bytes"] or 0) / 1e6,
             (v["write_bytes"] or 0) / 1e6))
     lines += ["", "Kernel source hash: %s" % rec["source_hash"]]
-    with open(os.path.join(ROOT, "profiles", "kernels_single_tensor_256MiB.md"), "w") as f:
+    with open(os.path.join(OUT, "kernels_single_tensor_256MiB.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

@@ -260,7 +260,7 @@ size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint
   if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return 0;
   const uint64_t segs = (total_symbols >> log2_seg) + n_jobs;
-  const uint64_t groups = (total_symbols >> (log2c + 7)) + n_jobs;
+  const uint64_t groups = (total_symbols >> (log2c + kDecThreadsLog2)) + n_jobs;
   const uint64_t enc = segs * kBatchSegBytes, dec = groups * kBatchGroupBytes;
   return round256(batch_units_offset(n_jobs) + (enc > dec ? enc : dec));
 }
@@ -294,7 +294,7 @@ qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chu
   if (n_jobs == 0) return QLC_OK;
   if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
   BatchView v = carve_batch(ws, ws_bytes, n_jobs, true);
-  hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + 7, v.max_units, 0, v.hdr, v.js,
+  hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + kDecThreadsLog2, v.max_units, 0, v.hdr, v.js,
                                    v.job_hist, v.unit_job, nullptr, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
   return hip_status(launch_decode_batched(jobs, log2c, v.hdr, v.js, v.unit_job,

@@ -136,6 +136,16 @@ __device__ __forceinline__ void set_error(uint32_t* slot, uint32_t code) {
   __builtin_amdgcn_s_waitcnt(0);
 }
 
+// set_error for a wave: one atomic from the first lane with `bad` set, and
+// none once the slot already holds an error (keeps a corrupt input from
+// serialising every lane on one address).
+__device__ __forceinline__ void set_error_wave(uint32_t* slot, uint32_t code, bool bad) {
+  const uint64_t m = __ballot(bad);
+  if (m == 0) return;
+  if ((threadIdx.x & 63) == (uint32_t)__builtin_ctzll(m) && load_relaxed_u32(slot) == 0)
+    set_error(slot, code);
+}
+
 // 32 bits of the concatenation hi:lo starting r bits below the top of hi.
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t r) {
   return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> (32 - r));

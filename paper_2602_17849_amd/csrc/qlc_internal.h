@@ -15,8 +15,17 @@ constexpr int kTableThreads = 512;    // table-building workgroup
 constexpr int kEncThreads = 256;      // encode workgroup
 constexpr int kEncSymsPerThread = 32; // two 16-byte loads per thread
 constexpr int kEncTile = kEncThreads * kEncSymsPerThread;  // symbols per tile
-constexpr int kDecThreads = 128;      // decode workgroup: one lane per chunk
+#ifndef QLC_DEC_THREADS_LOG2
+#define QLC_DEC_THREADS_LOG2 8
+#endif
+#ifndef QLC_DEC_STAGE_GROUPS
+#define QLC_DEC_STAGE_GROUPS 16
+#endif
+constexpr int kDecThreadsLog2 = QLC_DEC_THREADS_LOG2;
+constexpr int kDecThreads = 1 << kDecThreadsLog2;  // decode workgroup: one lane per chunk
 constexpr int kDecGroup = 8;          // symbols decoded per window refill
+constexpr int kStageGroups = QLC_DEC_STAGE_GROUPS;  // decoded groups staged per lane (8 or 16)
+static_assert(kStageGroups == 8 || kStageGroups == 16, "stage depth");
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies
 
 // ---- histogram kernel outputs ----------------------------------------------

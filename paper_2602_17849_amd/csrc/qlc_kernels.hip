@@ -547,38 +547,47 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // Decode (Implementation section: 3 bits give the area and thus the suffix
 // width; suffix + offset = rank; rank -> symbol via the decoder LUT).
 //
-// One lane per chunk, 128 chunks per workgroup.  The decoder LUT is
-// re-indexed by the whole code word: because widths never decrease, the
-// codes of area a occupy the integer range [a << w_a, (a + 1) << w_a) and
-// these ranges are disjoint, so a 2048-entry LDS table maps code -> symbol
-// (bit 15 flags an invalid suffix).  The per-symbol chain is pure VALU: the
-// 3-bit area code selects the shift 29 - w_a from an 8-byte register table
-// (v_perm), the code is the window shifted right by it, and three funnel
-// shifts advance a 96-bit window by 3 + w_a bits.
+// One lane per chunk, kDecThreads (256) chunks per workgroup.  The decoder
+// LUT is re-indexed by the whole code word: because widths never decrease,
+// the codes of area a occupy the integer range [a << w_a, (a + 1) << w_a)
+// and these ranges are disjoint, so a 2048-entry LDS table maps code ->
+// symbol (bit 15 flags an invalid suffix).  The per-symbol chain is pure
+// VALU: the 3-bit area code selects the shift 29 - w_a from an 8-byte
+// register table (v_perm), the code is the window shifted right by it, and
+// three funnel shifts advance a 96-bit window by 3 + w_a bits.
 //
 // Memory: each lane streams its chunk in 64-byte superblocks (four 16-byte
 // bounds-checked buffer loads of one aligned 64-byte line segment) into a
 // private 2-superblock LDS ring (plus a mirror of the first words, so a
-// 4-word window never wraps).  A superblock is loaded at most once per
-// 8-symbol group and written to the ring two groups after its load was
-// issued (two alternating register sets), so every wave waits at fixed
-// program points for loads that are two groups old.  Lanes that need no
-// superblock issue the loads with an out-of-range offset (zeros returned,
-// no memory touched).  Decoded bytes are staged per lane in LDS and, every
-// 8 groups, the wave stores all 64 lanes' 64-byte output runs with
-// coalesced stores (8 lanes per 64-byte run).
+// 4-word window never wraps), stored word-major so that window reads never
+// conflict on LDS banks.  A superblock is loaded at most once per 8-symbol
+// group; whole waves keep four register sets in rotation, so a superblock
+// is written to the ring four groups after its load was issued and every
+// wave waits at fixed program points for loads that old.  Lanes that need
+// no superblock issue the loads with an out-of-range offset (zeros
+// returned, no memory touched).  Decoded bytes are staged per lane in LDS
+// and, every kStageGroups (16) groups, the wave stores its 64 lanes'
+// 128-byte output runs with coalesced stores (16 lanes per run, whole
+// 128-byte lines).
 // ===========================================================================
 constexpr int kDecLanes = kDecThreads;     // chunks per workgroup
-constexpr int kRingStride = 36;            // 2 x 16 ring words + 4 mirror words
+constexpr int kRingWords = 36;             // 2 x 16 ring words + 4 mirror words
 constexpr uint32_t kLookaheadBits = 512;
 constexpr uint32_t kOobOffset = 0xFFFFFFC0u;
 constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
 
 struct DecSmem {
   uint16_t lut[2048];
-  uint32_t ring[kDecLanes * kRingStride];
-  uint2 stage[kDecLanes * 8];               // 8 groups x 8 bytes per lane
+  uint32_t ring[kDecLanes * kRingWords];
+  uint2 stage[kDecLanes * kStageGroups];    // kStageGroups groups x 8 bytes per lane
 };
+
+// Staging slot of group g of lane t: rotated by the lane so that the 8-byte
+// writes of a wave, and the reads of the coalesced flush, hit distinct LDS
+// banks.
+__device__ __forceinline__ uint32_t stage_slot(uint32_t g, uint32_t t) {
+  return kStageGroups == 8 ? ((g ^ (t >> 2)) & 7u) : ((g ^ (t >> 1)) & 15u);
+}
 
 struct Superblock {
   uint4 q0, q1, q2, q3;
@@ -599,14 +608,23 @@ __device__ __forceinline__ Superblock load_sb(__amdgpu_buffer_rsrc_t rsrc, uint3
 }
 
 // Superblock `sb` (absolute number) into ring slot sb & 1 (words 16*(sb&1)),
-// in memory byte order (the window reads swap to most-significant-first).
+// in memory byte order (the window reads swap to most-significant-first);
+// slot 0's first four words are mirrored to words 32..35 so that a 4-word
+// window never wraps.
+// The ring is stored word-major ("transposed"): word w of lane l sits at
+// ring[w * kDecLanes + l], so every lane only ever touches LDS bank l mod 64
+// and the window reads of a wave are free of bank conflicts whatever the
+// lanes' positions.
 __device__ __forceinline__ void ring_put(uint32_t* ring, uint32_t sb, const Superblock& s) {
-  uint4* r = reinterpret_cast<uint4*>(ring + (sb & 1u) * 16u);
-  r[0] = s.q0;
-  r[1] = s.q1;
-  r[2] = s.q2;
-  r[3] = s.q3;
-  if ((sb & 1u) == 0) *reinterpret_cast<uint4*>(ring + 32) = s.q0;
+  uint32_t* r = ring + (sb & 1u) * 16u * kDecLanes;
+  const uint32_t v[16] = {s.q0.x, s.q0.y, s.q0.z, s.q0.w, s.q1.x, s.q1.y, s.q1.z, s.q1.w,
+                          s.q2.x, s.q2.y, s.q2.z, s.q2.w, s.q3.x, s.q3.y, s.q3.z, s.q3.w};
+#pragma unroll
+  for (int i = 0; i < 16; ++i) r[i * kDecLanes] = v[i];
+  if ((sb & 1u) == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ring[(32 + i) * kDecLanes] = v[i];
+  }
 }
 
 struct DecLane {
@@ -620,8 +638,9 @@ struct DecLane {
 __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
   const uint32_t q = (uint32_t)L.pm1;
   const uint32_t wi = (q >> 5) & 31u;
-  const uint32_t w0 = __builtin_bswap32(L.ring[wi]), w1 = __builtin_bswap32(L.ring[wi + 1]);
-  const uint32_t w2 = __builtin_bswap32(L.ring[wi + 2]), w3 = __builtin_bswap32(L.ring[wi + 3]);
+  const uint32_t* rr = L.ring + wi * kDecLanes;
+  const uint32_t w0 = __builtin_bswap32(rr[0]), w1 = __builtin_bswap32(rr[kDecLanes]);
+  const uint32_t w2 = __builtin_bswap32(rr[2 * kDecLanes]), w3 = __builtin_bswap32(rr[3 * kDecLanes]);
   const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - (pos & 31), or 0
   uint32_t A = __builtin_amdgcn_alignbit(w0, w1, sh0);
   uint32_t B = __builtin_amdgcn_alignbit(w1, w2, sh0);
@@ -680,11 +699,10 @@ __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ tabl
   }
 }
 
-// Decode chunk group `grp` (chunks 128*grp .. 128*grp+127, one per lane;
-// tid = threadIdx.x)
-// of an n-symbol stream; S.lut holds the code -> symbol LUT.  Returns true
-// in a lane whose chunk is corrupt (or whose index entries are
-// inconsistent).
+// Decode chunk group `grp` of an n-symbol stream: chunks kDecThreads*grp
+// onwards, one per lane (tid = threadIdx.x); S.lut holds the code -> symbol
+// LUT.  Returns true in a lane whose chunk is corrupt (or whose index
+// entries are inconsistent).
 __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, uint64_t total,
                              const uint64_t* __restrict__ index, uint32_t log2_chunk, uint64_t n,
                              uint8_t* __restrict__ out, uint64_t grp, uint32_t sh_lo,
@@ -733,7 +751,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     }
     const bool live = (j < nchunks) && !bad;
     DecLane L;
-    L.ring = S.ring + tid * kRingStride;
+    L.ring = S.ring + tid;
     L.pm1 = (live ? pos0 : 0) - 1;
     L.sh_lo = sh_lo;
     L.sh_hi = sh_hi;
@@ -751,8 +769,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     Superblock pa, pb;
     uint32_t sba = 0, sbb = 0;
     bool va = false, vb = false;
-    uint2* stage = S.stage + tid * 8;
-    const uint32_t sw = tid >> 2;  // staging slot swizzle: 2-way LDS bank sharing at most
+    uint2* stage = S.stage + tid * kStageGroups;
     uint8_t* o = out + (j << log2_chunk);
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
@@ -768,7 +785,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
 #define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
   {                                                                                     \
     const uint32_t gg = (gidx);                                                         \
-    if (gg < my_groups) stage[(gg ^ sw) & 7u] = decode_group(L, S.lut);                 \
+    if (gg < my_groups) stage[stage_slot(gg, tid)] = decode_group(L, S.lut);            \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
     VAL = live && gg < my_groups &&                                                     \
           ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
@@ -780,31 +797,36 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     // Waves whose 64 chunks are all whole and valid (all but at most the
     // last wave) take a branch-free path with four register sets in
     // rotation: a superblock is written to the ring four groups after its
-    // load was issued.  Every 8 groups the wave stores its 64 lanes'
-    // 64-byte output runs, 8 consecutive lanes per run.
+    // load was issued.  Every kStageGroups groups the wave stores its 64
+    // lanes' output runs (8 * kStageGroups bytes each), kStageGroups
+    // consecutive lanes per run.
     const bool full_wave = __all(live && my_groups == wave_groups);
     if (full_wave) {
       Superblock pc_, pd_;
       uint32_t sbc = 0, sbd = 0;
       bool vc = false, vd = false;
-      uint8_t* obase = out + ((j_wave + (lane >> 3)) << log2_chunk) + (lane & 7u) * 8u;
+      constexpr uint32_t R = kStageGroups;      // lanes per output run
+      constexpr uint32_t kRuns = 64 / R;        // runs per store instruction
+      const uint32_t part = lane % R;
+      uint8_t* obase = out + ((j_wave + lane / R) << log2_chunk) + part * 8u;
 #pragma unroll 1
       for (uint32_t g = 0; g < wave_groups; g += 4) {
-        stage[((g + 0) ^ sw) & 7u] = decode_group(L, S.lut);
+        stage[stage_slot(g + 0, tid)] = decode_group(L, S.lut);
         QLC_DEC_REFILL(va, sba, pa)
-        stage[((g + 1) ^ sw) & 7u] = decode_group(L, S.lut);
+        stage[stage_slot(g + 1, tid)] = decode_group(L, S.lut);
         QLC_DEC_REFILL(vb, sbb, pb)
-        stage[((g + 2) ^ sw) & 7u] = decode_group(L, S.lut);
+        stage[stage_slot(g + 2, tid)] = decode_group(L, S.lut);
         QLC_DEC_REFILL(vc, sbc, pc_)
-        stage[((g + 3) ^ sw) & 7u] = decode_group(L, S.lut);
+        stage[stage_slot(g + 3, tid)] = decode_group(L, S.lut);
         QLC_DEC_REFILL(vd, sbd, pd_)
-        if ((g & 7u) == 4u) {
+        if ((g & (R - 1)) == R - 4) {
+          const uint32_t g0 = g + 4 - R;
           __builtin_amdgcn_wave_barrier();
 #pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const uint32_t stid = (tid & ~63u) | ((lane >> 3) + 8u * k);
-            const uint2 v = S.stage[stid * 8 + (((lane & 7u) ^ (stid >> 2)) & 7u)];
-            *reinterpret_cast<uint2*>(obase + ((uint64_t)(8 * k) << log2_chunk) + (g - 4) * 8) = v;
+          for (uint32_t k = 0; k < R; ++k) {
+            const uint32_t stid = (tid & ~63u) | (lane / R + kRuns * k);
+            const uint2 v = S.stage[stid * R + stage_slot(g0 + part, stid)];
+            *reinterpret_cast<uint2*>(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8) = v;
           }
           __builtin_amdgcn_wave_barrier();
         }
@@ -827,7 +849,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
           const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
           const uint32_t part = lane & 7u;                      // 8-byte piece of the run
           const uint32_t stid = (tid & ~63u) | src;
-          const uint2 v = S.stage[stid * 8 + ((part ^ (stid >> 2)) & 7u)];
+          const uint2 v = S.stage[stid * kStageGroups + stage_slot(g + part, stid)];
           const uint64_t jj = grp * kDecThreads + stid;
           const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
           if (g + part < ngrp)
@@ -843,8 +865,9 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     if (live && rem) {  // final partial group of the last chunk
       const uint32_t q = (uint32_t)L.pm1;
       const uint32_t wi = (q >> 5) & 31u;
-      const uint32_t w0 = __builtin_bswap32(L.ring[wi]), w1 = __builtin_bswap32(L.ring[wi + 1]);
-      const uint32_t w2 = __builtin_bswap32(L.ring[wi + 2]), w3 = __builtin_bswap32(L.ring[wi + 3]);
+      const uint32_t* rr = L.ring + wi * kDecLanes;
+      const uint32_t w0 = __builtin_bswap32(rr[0]), w1 = __builtin_bswap32(rr[kDecLanes]);
+      const uint32_t w2 = __builtin_bswap32(rr[2 * kDecLanes]), w3 = __builtin_bswap32(rr[3 * kDecLanes]);
       uint32_t A = __builtin_amdgcn_alignbit(w0, w1, ~q);
       uint32_t B = __builtin_amdgcn_alignbit(w1, w2, ~q);
       uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, ~q);
@@ -879,7 +902,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
                                 sh_hi, S, tid);
 
   // ---- error word: first error wins; the last workgroup publishes it ----
-  if (bad) set_error(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM);
+  set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
   __syncthreads();
   if (tid == 0) {
     const uint32_t done = atomic_add_u32(&hdr->dec_done, 1u);
@@ -895,7 +918,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
 // Batched form: many jobs of uneven sizes per launch.
 //
 // A one-workgroup plan kernel numbers the jobs' work units (encode
-// segments of 2^log2_seg symbols, or decode groups of 128 chunks), records
+// segments of 2^log2_seg symbols, or decode groups of kDecThreads chunks), records
 // which job owns each unit and resets the per-call state.  The persistent
 // kernels then hand out work items from one atomic ticket counter.
 //
@@ -1178,7 +1201,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     }
     const bool bad = decode_block(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk, jb.n,
                                   jb.out, p - js[k].base, sh_lo, sh_hi, S, opaque_tid());
-    if (bad) set_error(jb.err, QLC_ERR_CORRUPT_STREAM);
+    set_error_wave(jb.err, QLC_ERR_CORRUPT_STREAM, bad);
     __syncthreads();
   }
 }
