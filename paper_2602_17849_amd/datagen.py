@@ -155,5 +155,30 @@ def serving_requests(duration_s: float = 10.0, rate: float = 2000.0, seed: int =
     return out
 
 
+STRESS_KINDS = {"uniform": 4, "zeros90": 5, "ocp_gaussian": 6}
+
+
+def stress_buffer(kind: str, numel: int = 1 << 32, device="cpu",
+                  piece: int = 1 << 28) -> torch.Tensor:
+    """The 4 GiB stress buffers, generated in pieces of `piece` symbols
+    (piece k of a buffer with seed s uses seed s * 1000 + k):
+    ``uniform`` random bytes (seed 4), ``zeros90`` N(0,1) e4m3 with 90 % of
+    the bytes forced to 0x00 (seed 5), ``ocp_gaussian`` N(0,1) block-32 e4m3
+    under the 448 scale rule (seed 6), which never emits 0x7F / 0xFF."""
+    seed = STRESS_KINDS[kind]
+    out = torch.empty(numel, dtype=torch.uint8, device=device)
+    for k, p0 in enumerate(range(0, numel, piece)):
+        m = min(piece, numel - p0)
+        m32 = (m + 31) // 32 * 32          # whole quantisation blocks
+        s = seed * 1000 + k
+        if kind == "uniform":
+            out[p0:p0 + m] = uniform_bytes(m32, s, device)[:m]
+        elif kind == "zeros90":
+            out[p0:p0 + m] = zeros90_gaussian(m32, s, device)[:m]
+        else:
+            out[p0:p0 + m] = gaussian(m32, s, device)[:m]
+    return out
+
+
 def sha256(x: torch.Tensor) -> str:
     return hashlib.sha256(x.detach().cpu().contiguous().numpy().tobytes()).hexdigest()

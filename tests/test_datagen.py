@@ -53,3 +53,17 @@ def test_workload_shapes():
     z = datagen.zeros90_gaussian(1 << 16, seed=5)
     frac = (z == 0).float().mean().item()
     assert 0.88 < frac < 0.93
+
+
+def test_stress_buffer_pieces():
+    """The 4 GiB stress recipe, at a small size: deterministic, piecewise
+    seeded, kind-specific structure."""
+    for kind in datagen.STRESS_KINDS:
+        a = datagen.stress_buffer(kind, numel=5000, piece=1024)
+        b = datagen.stress_buffer(kind, numel=5000, piece=1024)
+        assert a.numel() == 5000 and torch.equal(a, b)
+        assert not torch.equal(a[:1024], a[1024:2048])     # pieces use their own seeds
+    z = datagen.stress_buffer("zeros90", numel=1 << 16, piece=1 << 14)
+    assert 0.88 < (z == 0).float().mean().item() < 0.93
+    g = datagen.stress_buffer("ocp_gaussian", numel=1 << 16, piece=1 << 14)
+    assert not ((g == 0x7F) | (g == 0xFF)).any()
