@@ -634,35 +634,63 @@ struct DecLane {
   uint32_t errbits;
 };
 
-// Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
-__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
-  const uint32_t q = (uint32_t)L.pm1;
-  const uint32_t wi = (q >> 5) & 31u;
-  const uint32_t* rr = L.ring + wi * kDecLanes;
-  const uint32_t w0 = __builtin_bswap32(rr[0]), w1 = __builtin_bswap32(rr[kDecLanes]);
-  const uint32_t w2 = __builtin_bswap32(rr[2 * kDecLanes]), w3 = __builtin_bswap32(rr[3 * kDecLanes]);
+struct Window {
+  uint32_t w0, w1, w2, w3;
+};
+
+// The four ring words holding bits pm1 + 1 .. pm1 + 96 (q = pm1, in the
+// ring's coordinates), as stored (memory byte order).
+__device__ __forceinline__ Window window_read(const uint32_t* ring, uint32_t q) {
+  const uint32_t* rr = ring + ((q >> 5) & 31u) * kDecLanes;
+  Window w;
+  w.w0 = rr[0];
+  w.w1 = rr[kDecLanes];
+  w.w2 = rr[2 * kDecLanes];
+  w.w3 = rr[3 * kDecLanes];
+  return w;
+}
+
+// The 8-symbol chain on a window read at q = pm1: e[k] receives the LUT
+// entries (gathers issued, not waited for); returns the bits consumed.
+__device__ __forceinline__ uint32_t decode_chain(const Window& W, uint32_t q, uint32_t sh_lo,
+                                                 uint32_t sh_hi, const uint16_t* __restrict__ lut,
+                                                 uint32_t (&e)[8]) {
+  const uint32_t w0 = __builtin_bswap32(W.w0), w1 = __builtin_bswap32(W.w1);
+  const uint32_t w2 = __builtin_bswap32(W.w2), w3 = __builtin_bswap32(W.w3);
   const uint32_t sh0 = ~q;  // alignbit uses the low 5 bits: 32 - (pos & 31), or 0
   uint32_t A = __builtin_amdgcn_alignbit(w0, w1, sh0);
   uint32_t B = __builtin_amdgcn_alignbit(w1, w2, sh0);
   uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, sh0);
-  uint32_t e[8];
   uint32_t ssum = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
-    const uint32_t s = __builtin_amdgcn_perm(L.sh_hi, L.sh_lo, sel);  // 29 - width
-    e[k] = lut[A >> s];
-    A = __builtin_amdgcn_alignbit(A, B, s);
-    B = __builtin_amdgcn_alignbit(B, Cw, s);
-    Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
-    ssum += s;
+    const uint32_t sft = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);  // 29 - width
+    e[k] = lut[A >> sft];
+    A = __builtin_amdgcn_alignbit(A, B, sft);
+    B = __builtin_amdgcn_alignbit(B, Cw, sft);
+    Cw = __builtin_amdgcn_alignbit(Cw, 0u, sft);
+    ssum += sft;
   }
-  L.pm1 += 256u - ssum;  // 8 codes of 32 - s bits each
+  return 256u - ssum;
+}
+
+// The 8 decoded bytes packed little-endian; the entries' invalid flags are
+// accumulated in errbits.
+__device__ __forceinline__ uint2 pack_group(const uint32_t (&e)[8], uint32_t& errbits) {
   uint2 r;
   r.x = __builtin_amdgcn_perm(e[1], e[0], 0x0C0C0400u) | __builtin_amdgcn_perm(e[3], e[2], 0x04000C0Cu);
   r.y = __builtin_amdgcn_perm(e[5], e[4], 0x0C0C0400u) | __builtin_amdgcn_perm(e[7], e[6], 0x04000C0Cu);
-  L.errbits |= e[0] | e[1] | e[2] | e[3] | e[4] | e[5] | e[6] | e[7];
+  errbits |= e[0] | e[1] | e[2] | e[3] | e[4] | e[5] | e[6] | e[7];
   return r;
+}
+
+// Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
+__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
+  const uint32_t q = (uint32_t)L.pm1;
+  uint32_t e[8];
+  L.pm1 += decode_chain(window_read(L.ring, q), q, L.sh_lo, L.sh_hi, lut, e);
+  return pack_group(e, L.errbits);
 }
 
 // Code -> symbol LUT of `table` into `lut` (2048 entries, bit 15 = invalid
@@ -809,16 +837,32 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       constexpr uint32_t kRuns = 64 / R;        // runs per store instruction
       const uint32_t part = lane % R;
       uint8_t* obase = out + ((j_wave + lane / R) << log2_chunk) + part * 8u;
+      // Software pipelined: the next group's window is read right after the
+      // current chain (and after the ring write it may depend on), so its
+      // LDS latency overlaps the current group's LUT gathers and packing.
+      // Positions are 32-bit, relative to the wave's first superblock.
+      uint32_t q = (uint32_t)(L.pm1 - rel0);
+      const uint32_t* ring = L.ring;
+      const uint32_t rs = (uint32_t)base_sb & 1u;  // ring slot parity of relative superblocks
+      Window W = window_read(ring, q + (rs << 9));
+#define QLC_DEC_UNIT(GI, VAL, SBX, PX)                                                  \
+  {                                                                                     \
+    uint32_t e[8];                                                                      \
+    q += decode_chain(W, q, L.sh_lo, L.sh_hi, S.lut, e);                                \
+    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
+    W = window_read(ring, q + (rs << 9));                                               \
+    VAL = (fsb << 9) < q + 1 + kLookaheadBits;                                          \
+    SBX = fsb;                                                                          \
+    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    fsb += VAL ? 1u : 0u;                                                               \
+    stage[stage_slot((GI), tid)] = pack_group(e, L.errbits);                            \
+  }
 #pragma unroll 1
       for (uint32_t g = 0; g < wave_groups; g += 4) {
-        stage[stage_slot(g + 0, tid)] = decode_group(L, S.lut);
-        QLC_DEC_REFILL(va, sba, pa)
-        stage[stage_slot(g + 1, tid)] = decode_group(L, S.lut);
-        QLC_DEC_REFILL(vb, sbb, pb)
-        stage[stage_slot(g + 2, tid)] = decode_group(L, S.lut);
-        QLC_DEC_REFILL(vc, sbc, pc_)
-        stage[stage_slot(g + 3, tid)] = decode_group(L, S.lut);
-        QLC_DEC_REFILL(vd, sbd, pd_)
+        QLC_DEC_UNIT(g + 0, va, sba, pa)
+        QLC_DEC_UNIT(g + 1, vb, sbb, pb)
+        QLC_DEC_UNIT(g + 2, vc, sbc, pc_)
+        QLC_DEC_UNIT(g + 3, vd, sbd, pd_)
         if ((g & (R - 1)) == R - 4) {
           const uint32_t g0 = g + 4 - R;
           __builtin_amdgcn_wave_barrier();
@@ -831,6 +875,8 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
           __builtin_amdgcn_wave_barrier();
         }
       }
+#undef QLC_DEC_UNIT
+      L.pm1 = rel0 + q;
       if (vc) ring_put(L.ring, sb0 + sbc, pc_);
       if (vd) ring_put(L.ring, sb0 + sbd, pd_);
     } else {
