@@ -80,13 +80,17 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan_u64(uint64_t v) {
   return v;
 }
 
+// Inclusive wave64 scan with DPP: a Hillis-Steele scan inside each 16-lane
+// row (row_shr 1, 2, 4, 8; lanes shifted in from outside the row add 0),
+// then row 0's total into row 1 and row 2's into row 3 (row_bcast:15), then
+// rows 0-1's total into rows 2 and 3 (row_bcast:31).  No LDS round trips.
 __device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 

@@ -294,12 +294,19 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
 // segment (the last segment pads and stores it).
 // ===========================================================================
 struct EncSmem {
-  uint16_t lut[256];
-  uint32_t words[kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
+  uint32_t lut[256];        // code | length << 16 (halves feed SDWA operands)
+  __attribute__((aligned(16))) uint32_t words[kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
   uint64_t red[kEncThreads / 64];
   uint32_t wave_sum[kEncThreads / 64];
   uint32_t seg, epoch, cap_hit, bad_table;
 };
+
+// Encoder LUT entry of a table's (len << 11) | code word: code | len << 16.
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t enc_entry(uint32_t e) {
+  return (e & 0x7FFu) | ((e >> 11) << 16);
+}
 
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   v = wave_sum_u64(v);
@@ -353,13 +360,21 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
       uint64_t acc = 0;
       for (int k = 16; k >= 1; --k) {
         const uint32_t e = S.lut[in[seg0 - k]];
-        acc = (acc << (e >> 11)) | (e & 0x7FFu);
+        acc = (acc << (e >> 16)) | (e & 0xFFFFu);
       }
       w0 = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
     }
     S.words[0] = w0;
   }
   uint64_t R = G;  // global bit offset of the current tile
+  // Output through a buffer resource based at the segment's first word
+  // (segment-relative offsets stay far below 2^32): stores at or past
+  // cap_words are dropped by the hardware.
+  const uint64_t seg_w0 = G >> 5;
+  const uint64_t room = cap_words > seg_w0 ? (cap_words - seg_w0) * 4 : 0;
+  const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      bits_out + (cap_words > seg_w0 ? seg_w0 : 0), (short)0,
+      (int)(uint32_t)(room < 0xFFFFFFF0ull ? room : 0xFFFFFFF0ull), 0x00020000);
   const uint64_t cmask = (1ull << log2_chunk) - 1;
   uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
   if (seg0 + kEncTile <= seg1) {
@@ -384,9 +399,9 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
         const uint32_t w = sw[k >> 1];
         const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
         const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
-        const uint32_t l1 = e1 >> 11;
-        pc[k] = ((e0 & 0x7FFu) << l1) | (e1 & 0x7FFu);
-        pl[k] = (e0 >> 11) + l1;
+        const uint32_t l1 = e1 >> 16;
+        pc[k] = ((e0 & 0xFFFFu) << l1) | (e1 & 0xFFFFu);
+        pl[k] = (e0 >> 16) + l1;
         if (k < 8) b0 += pl[k];
         else b1 += pl[k];
       }
@@ -395,7 +410,7 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
 #pragma unroll 1
       for (int k = 0; k < 32; ++k) {
         const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-        const uint32_t l = i < seg1 ? ((uint32_t)S.lut[in[i]] >> 11) : 0u;
+        const uint32_t l = i < seg1 ? (S.lut[in[i]] >> 16) : 0u;
         if (k < 16) b0 += l;
         else b1 += l;
       }
@@ -436,8 +451,8 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
               t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
           if (i < seg1) {
             const uint32_t e = S.lut[in[i]];
-            if (k < 16) P0.put(S.words, e & 0x7FFu, e >> 11);
-            else P1.put(S.words, e & 0x7FFu, e >> 11);
+            if (k < 16) P0.put(S.words, e & 0xFFFFu, e >> 16);
+            else P1.put(S.words, e & 0xFFFFu, e >> 16);
           }
         }
       }
@@ -455,11 +470,25 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
     const uint32_t endb = g + tile_bits;
     const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
     const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
-    const uint64_t w0 = R >> 5;
-    for (uint32_t i = tid; i < nw; i += kEncThreads) {
-      if (w0 + i < cap_words) bits_out[w0 + i] = __builtin_bswap32(S.words[i]);
-      else cap = true;
-      S.words[i] = 0;
+    const uint32_t wr = (uint32_t)((R >> 5) - seg_w0);  // tile's first word, segment-relative
+    if (tid == 0 && (R >> 5) + nw > cap_words) cap = true;
+    // four words per thread per store; the buffer resource drops anything
+    // past the capacity
+    for (uint32_t i = 4 * tid; i < nw; i += 4 * kEncThreads) {
+      uint4* src = reinterpret_cast<uint4*>(&S.words[i]);
+      if (i + 4 <= nw) {
+        const uint4 v = *src;
+        *src = make_uint4(0, 0, 0, 0);
+        const v4u32 o = {__builtin_bswap32(v.x), __builtin_bswap32(v.y), __builtin_bswap32(v.z),
+                         __builtin_bswap32(v.w)};
+        __builtin_amdgcn_raw_buffer_store_b128(o, out_rsrc, (wr + i) * 4, 0, 0);
+      } else {
+        for (uint32_t k = i; k < nw; ++k) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bswap32(S.words[k]), out_rsrc,
+                                                (wr + k) * 4, 0, 0);
+          S.words[k] = 0;
+        }
+      }
     }
     __syncthreads();
     if (tid == 0 && !final_tile) {
@@ -491,7 +520,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     S.bad_table = 0;
   }
   const uint32_t e_t = table->enc[tid];
-  S.lut[tid] = (uint16_t)e_t;
+  S.lut[tid] = enc_entry(e_t);
   for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) S.words[w] = 0;
   __syncthreads();
   // A table whose code lengths leave 3..11 is rejected (keeps every LDS
@@ -1190,14 +1219,14 @@ __global__ __launch_bounds__(kEncThreads) void k_encode_batched(
       if (tid < 128) {
         const uint32_t* tw = reinterpret_cast<const uint32_t*>(jb.table);
         const uint32_t w = load_relaxed_u32(&tw[tid]);
-        S.enc.lut[2 * tid] = (uint16_t)w;
-        S.enc.lut[2 * tid + 1] = (uint16_t)(w >> 16);
+        S.enc.lut[2 * tid] = enc_entry(w & 0xFFFFu);
+        S.enc.lut[2 * tid + 1] = enc_entry(w >> 16);
       }
       __syncthreads();
-      const uint32_t e_t = S.enc.lut[tid];
-      if ((e_t >> 11) < 3 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
+      const uint32_t len_t = S.enc.lut[tid] >> 16;
+      if (len_t < 3 || len_t > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
       const uint64_t my_bits = block_sum_u64(
-          (uint64_t)load_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid]) * (e_t >> 11), S.enc.red);
+          (uint64_t)load_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid]) * len_t, S.enc.red);
       const bool bad_table = S.enc.bad_table != 0;
       if (tid == 0) store_relaxed_u64(&seg_word[g], (1ull << 63) | my_bits);
       uint64_t pre = 0;
