@@ -871,6 +871,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       // LDS latency overlaps the current group's LUT gathers and packing.
       // Positions are 32-bit, relative to the wave's first superblock.
       uint32_t q = (uint32_t)(L.pm1 - rel0);
+      const uint32_t endr = (uint32_t)(end - rel0);  // no superblock past the chunk's end
       const uint32_t* ring = L.ring;
       const uint32_t rs = (uint32_t)base_sb & 1u;  // ring slot parity of relative superblocks
       Window W = window_read(ring, q + (rs << 9));
@@ -880,7 +881,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     q += decode_chain(W, q, L.sh_lo, L.sh_hi, S.lut, e);                                \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
     W = window_read(ring, q + (rs << 9));                                               \
-    VAL = (fsb << 9) < q + 1 + kLookaheadBits;                                          \
+    VAL = (fsb << 9) < min(q + 1 + kLookaheadBits, endr);                               \
     SBX = fsb;                                                                          \
     PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
     fsb += VAL ? 1u : 0u;                                                               \
