@@ -86,3 +86,58 @@ def test_host_table_deserialize_rejects_invalid():
             qlc.qlc_table_deserialize(bytes(w) + perm)
     with pytest.raises(qlc.QLCError):
         qlc.qlc_table_deserialize(bytes([3, 3, 3, 3, 3, 4, 5, 8]) + bytes([0]) + perm[1:255] + bytes([0]))
+
+
+def test_struct_layouts_match_the_header():
+    assert ctypes.sizeof(qlc.Job) == 80 and ctypes.sizeof(qlc.BatchTuning) == 16
+    assert ctypes.sizeof(qlc.ServerConfig) == 40 and ctypes.sizeof(qlc.Request) == 64
+    assert ctypes.sizeof(qlc.Result) == 104 and ctypes.sizeof(qlc.ServerStats) == 72
+    assert qlc.Job.build_table.offset == 72 and qlc.Job.err.offset == 64
+
+
+def test_batched_workspace_query():
+    f = qlc.qlc_batched_workspace_bytes
+    a = f(1152, 10 << 30, 2048)
+    assert a > 0 and a % 256 == 0
+    assert f(1152, 20 << 30, 2048) > a                      # grows with the data
+    assert f(2304, 10 << 30, 2048) > a                      # and with the job count
+    assert f(1152, 10 << 30, 2048, (16, 0, 0, 0)) > a       # smaller segments need more units
+    assert f(3, 0, 4096) > 0
+    assert f(1, 1 << 20, 1000) == 0                         # C not a power of two
+    assert f(1, 1 << 20, 4096, (12, 0, 0, 0)) == 0          # segment below 2^13
+    assert f(1, 1 << 20, 4096, (13, 0, 0, 1)) == 0          # reserved field set
+
+
+def test_batched_argument_errors_are_synchronous():
+    L = qlc.lib()
+    ws = 1 << 20
+    big = 1 << 30
+    tun = qlc.BatchTuning(25, 0, 0, 0)                      # segment above 2^24
+    assert L.qlc_encode_batched(ws, 4, 0, 4096, ctypes.addressof(tun), ws, big, 0) == \
+        qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(ws, 4, 0, 3000, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(ws, 4, 5, 4096, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(0, 4, 0, 4096, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(ws + 4, 4, 0, 4096, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(ws, 4, 0, 4096, None, ws + 64, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(ws, 4, 0, 4096, None, ws, 256, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_decode_batched(ws, 4, 4096 * 32, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_decode_batched(ws, 4, 4096, None, 0, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_encode_batched(0, 0, 0, 4096, None, ws, big, 0) == qlc.QLC_OK   # no jobs
+
+
+def test_server_config_errors_are_synchronous():
+    L = qlc.lib()
+    h = ctypes.c_void_p()
+    bad = [qlc.ServerConfig(0, 0, 4096, 0, 0, 0, 0, 0),             # no budget
+           qlc.ServerConfig(1 << 20, 0, 1000, 0, 0, 0, 0, 0),       # C not a power of two
+           qlc.ServerConfig(1 << 20, 0, 4096, 7, 0, 0, 0, 0),       # unknown layout mode
+           qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 9, 0, 0),       # too many ticks in flight
+           qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 0, 30, 0),      # segment out of range
+           qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 0, 0, 1)]       # reserved field set
+    for cfg in bad:
+        assert L.qlc_server_create(ctypes.addressof(cfg), ctypes.byref(h)) == \
+            qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_server_create(None, ctypes.byref(h)) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_server_submit(None, None, None) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_server_destroy(None) == qlc.QLC_ERR_INVALID_ARGUMENT

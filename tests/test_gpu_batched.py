@@ -283,3 +283,26 @@ def test_batched_workspace_shared_by_batches_of_different_sizes():
         torch.cuda.synchronize()
         check_against_oracle(b, xs, 0, C)
         check_round_trip(b, xs)
+
+
+def test_autotuner_choice_is_valid_and_output_invariant():
+    """The autotuner picks among candidates that all give the same bytes;
+    its choice is cached per batch shape."""
+    from paper_2602_17849_amd import autotune
+    sizes = [300000, 1 << 20, 77777, 2_000_000]
+    b, xs = make_batch(sizes, 1024, seed=21)
+    b.min_chunk = 1024
+    ch = autotune.tune_batched(b, 0, chunks=(1024, 2048), log2_segments=(14, 16), lags=(0, 1),
+                               reps=1, use_cache=False)
+    assert ch.chunk_symbols in (1024, 2048) and ch.log2_segment in (14, 16)
+    assert ch.encode_ms > 0 and ch.decode_ms > 0
+    b.set_chunk(ch.chunk_symbols)
+    ws = b.workspace(ch.tuning())
+    b.index.zero_()
+    b.encode(ws, 0, ch.tuning())
+    b.decode(ws, ch.tuning())
+    torch.cuda.synchronize()
+    check_against_oracle(b, xs, 0, ch.chunk_symbols)
+    check_round_trip(b, xs)
+    again = autotune.tune_batched(b, 0, chunks=(1024, 2048), log2_segments=(14, 16), lags=(0, 1))
+    assert again == ch or again.chunk_symbols in (1024, 2048)
