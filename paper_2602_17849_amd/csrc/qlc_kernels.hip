@@ -580,7 +580,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // LUT is re-indexed by the whole code word: because widths never decrease,
 // the codes of area a occupy the integer range [a << w_a, (a + 1) << w_a)
 // and these ranges are disjoint, so a 2048-entry LDS table maps code ->
-// symbol (bit 15 flags an invalid suffix).  The per-symbol chain is pure
+// symbol (bit 15 flags an invalid suffix; 32-bit entries, so gathered values
+// need no zero extension before packing).  The per-symbol chain is pure
 // VALU: the 3-bit area code selects the shift 29 - w_a from an 8-byte
 // register table (v_perm), the code is the window shifted right by it, and
 // three funnel shifts advance a 96-bit window by 3 + w_a bits.
@@ -606,7 +607,7 @@ constexpr uint32_t kOobOffset = 0xFFFFFFC0u;
 constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
 
 struct DecSmem {
-  uint16_t lut[2048];
+  uint32_t lut[2048];
   uint32_t ring[kDecLanes * kRingWords];
   uint2 stage[kDecLanes * kStageGroups];    // kStageGroups groups x 8 bytes per lane
 };
@@ -682,7 +683,7 @@ __device__ __forceinline__ Window window_read(const uint32_t* ring, uint32_t q) 
 // The 8-symbol chain on a window read at q = pm1: e[k] receives the LUT
 // entries (gathers issued, not waited for); returns the bits consumed.
 __device__ __forceinline__ uint32_t decode_chain(const Window& W, uint32_t q, uint32_t sh_lo,
-                                                 uint32_t sh_hi, const uint16_t* __restrict__ lut,
+                                                 uint32_t sh_hi, const uint32_t* __restrict__ lut,
                                                  uint32_t (&e)[8]) {
   const uint32_t w0 = __builtin_bswap32(W.w0), w1 = __builtin_bswap32(W.w1);
   const uint32_t w2 = __builtin_bswap32(W.w2), w3 = __builtin_bswap32(W.w3);
@@ -715,17 +716,17 @@ __device__ __forceinline__ uint2 pack_group(const uint32_t (&e)[8], uint32_t& er
 }
 
 // Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
-__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint16_t* __restrict__ lut) {
+__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __restrict__ lut) {
   const uint32_t q = (uint32_t)L.pm1;
   uint32_t e[8];
   L.pm1 += decode_chain(window_read(L.ring, q), q, L.sh_lo, L.sh_hi, lut, e);
   return pack_group(e, L.errbits);
 }
 
-// Code -> symbol LUT of `table` into `lut` (2048 entries, bit 15 = invalid
-// suffix) and the per-area shift table (byte a of sh_hi:sh_lo = 29 - width).
+// Code -> symbol LUT of `table` into `lut` (2048 32-bit entries, bit 15 =
+// invalid suffix) and the per-area shift table (byte a of sh_hi:sh_lo = 29 - width).
 // Any block size; the caller synchronises before using the LUT.
-__device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint16_t* lut,
+__device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint32_t* lut,
                               uint32_t& sh_lo, uint32_t& sh_hi) {
   sh_lo = 0;
   sh_hi = 0;
@@ -742,7 +743,7 @@ __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ tabl
       else sh_hi |= (29u - w[a]) << (8 * (a - 4));
     }
     for (uint32_t c = threadIdx.x; c < 2048; c += blockDim.x) {
-      uint16_t e = 0x8000;
+      uint32_t e = 0x8000;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
         if (c >= lo[a] && c < lo[a] + (1u << w[a])) {
