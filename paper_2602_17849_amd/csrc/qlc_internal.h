@@ -23,7 +23,6 @@ constexpr int kEncTile = kEncThreads * kEncSymsPerThread;  // symbols per tile
 #endif
 constexpr int kDecThreadsLog2 = QLC_DEC_THREADS_LOG2;
 constexpr int kDecThreads = 1 << kDecThreadsLog2;  // decode workgroup: one lane per chunk
-constexpr int kDecGroup = 8;          // symbols decoded per window refill
 constexpr int kStageGroups = QLC_DEC_STAGE_GROUPS;  // decoded groups staged per lane (8 or 16)
 static_assert(kStageGroups == 8 || kStageGroups == 16, "stage depth");
 constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies

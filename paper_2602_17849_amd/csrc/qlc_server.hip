@@ -354,7 +354,13 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
     delete s;
     return QLC_ERR_HIP;
   }
-  s->th = std::thread([s] { s->run(); });
+  try {
+    s->th = std::thread([s] { s->run(); });
+  } catch (...) {  // no exception may cross the C ABI
+    s->free_all();
+    delete s;
+    return QLC_ERR_HIP;
+  }
   *out = s;
   return QLC_OK;
 }
@@ -390,8 +396,14 @@ qlc_status qlc_server_submit(qlc_server* s, const qlc_request* h_req, uint64_t* 
   }
   q->id = s->next_id++;
   q->submit_ns = now_ns();
-  s->live[q->id] = q;
-  s->pending.push_back(q);
+  try {
+    s->live[q->id] = q;
+    s->pending.push_back(q);
+  } catch (...) {  // out of host memory: no exception may cross the C ABI
+    s->live.erase(q->id);
+    delete q;
+    return QLC_ERR_HIP;
+  }
   ++s->submitted;
   *id_out = q->id;
   s->cv_work.notify_one();
