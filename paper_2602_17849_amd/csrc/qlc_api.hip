@@ -208,10 +208,12 @@ qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
                                     chunk_index_out, total_bits_out, err_out, ws, ws_bytes, &log2c);
   if (st != QLC_OK) return st;
   WsView v = carve(ws, n);
-  hipError_t e = launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, nullptr, kHistSegment, 0,
-                                  nullptr, stream);
+  // segment bit counts straight from the table's lengths (the segment
+  // histograms' region holds them)
+  uint64_t* seg_bits = reinterpret_cast<uint64_t*>(v.seg_hist);
+  hipError_t e = launch_segment_bits(in, n, table, seg_bits, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode(in, n, table, v.seg_hist, log2c,
+  return hip_status(launch_encode(in, n, table, nullptr, seg_bits, log2c,
                                   reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
                                   chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
                                   stream));
@@ -231,7 +233,7 @@ qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode, qlc
                                   kHistSegment | kHistGlobal | kHistBuildTable, (uint32_t)mode,
                                   table_out, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode(in, n, table_out, v.seg_hist, log2c,
+  return hip_status(launch_encode(in, n, table_out, v.seg_hist, nullptr, log2c,
                                   reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
                                   chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
                                   stream));

@@ -503,11 +503,58 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
   return cap;
 }
 
+// Bit count of every segment under a given table (the pre-pass of an encode
+// with a fixed table): the segment's code lengths summed through an LDS
+// copy of the length column, no atomics.
+__global__ __launch_bounds__(kHistThreads) void k_segment_bits(
+    const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
+    const qlc_table* __restrict__ table, uint64_t* __restrict__ seg_bits) {
+  __shared__ uint32_t len[256];
+  __shared__ uint64_t red[kHistThreads / 64];
+  const uint32_t tid = threadIdx.x;
+  if (tid < 256) len[tid] = table->enc[tid] >> 11;
+  __syncthreads();
+  const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
+  const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
+  const uint4* vin = reinterpret_cast<const uint4*>(in);
+  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;
+  uint32_t s = 0;
+  uint64_t i = v0 + tid;
+  for (; i + 3 * kHistThreads < v1; i += 4 * kHistThreads) {
+    const uint4 a = vin[i], b = vin[i + kHistThreads];
+    const uint4 c = vin[i + 2 * kHistThreads], d = vin[i + 3 * kHistThreads];
+    const uint32_t w[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
+                            c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      s += len[w[k] & 0xFFu] + len[(w[k] >> 8) & 0xFFu] + len[(w[k] >> 16) & 0xFFu] +
+           len[w[k] >> 24];
+  }
+  for (; i < v1; i += kHistThreads) {
+    const uint4 a = vin[i];
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      s += len[w[k] & 0xFFu] + len[(w[k] >> 8) & 0xFFu] + len[(w[k] >> 16) & 0xFFu] +
+           len[w[k] >> 24];
+  }
+  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += kHistThreads) s += len[in[j]];
+  const uint64_t t = wave_sum_u64(s);
+  if ((tid & 63) == 0) red[tid >> 6] = t;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kHistThreads / 64; ++w) sum += red[w];
+    seg_bits[blockIdx.x] = sum;
+  }
+}
+
 __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
     const qlc_table* __restrict__ table, const uint32_t* __restrict__ seg_hist,
-    uint32_t log2_chunk, uint32_t* __restrict__ bits_out, uint64_t cap_words,
-    uint64_t* __restrict__ index_out, uint64_t* __restrict__ total_out,
+    const uint64_t* __restrict__ seg_bits, uint32_t log2_chunk, uint32_t* __restrict__ bits_out,
+    uint64_t cap_words, uint64_t* __restrict__ index_out, uint64_t* __restrict__ total_out,
     uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr, uint64_t* __restrict__ seg_word,
     uint32_t nseg) {
   __shared__ EncSmem S;
@@ -532,7 +579,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 
   // ---- this segment's bit count, published; the predecessors' summed ----
   const uint64_t my_bits =
-      block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
+      seg_bits ? seg_bits[seg]
+               : block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
   const bool bad_table = S.bad_table != 0;
   if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
   uint64_t pre = 0;
@@ -1315,13 +1363,21 @@ hipError_t launch_table_from_hist(const uint64_t* hist, uint32_t mode, qlc_table
 }
 
 hipError_t launch_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
-                         const uint32_t* seg_hist, uint32_t log2_chunk, uint32_t* bits_out,
-                         uint64_t cap_words, uint64_t* index_out, uint64_t* total_out,
-                         uint32_t* err_out, WsHeader* hdr, uint64_t* seg_word, hipStream_t stream) {
+                         const uint32_t* seg_hist, const uint64_t* seg_bits, uint32_t log2_chunk,
+                         uint32_t* bits_out, uint64_t cap_words, uint64_t* index_out,
+                         uint64_t* total_out, uint32_t* err_out, WsHeader* hdr, uint64_t* seg_word,
+                         hipStream_t stream) {
   const uint32_t nseg = (uint32_t)seg_count(n);
   hipLaunchKernelGGL(k_encode, dim3(nseg), dim3(kEncThreads), 0, stream, in, n, seg_log2(n), table,
-                     seg_hist, log2_chunk, bits_out, cap_words, index_out, total_out, err_out, hdr,
-                     seg_word, nseg);
+                     seg_hist, seg_bits, log2_chunk, bits_out, cap_words, index_out, total_out,
+                     err_out, hdr, seg_word, nseg);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_bits(const uint8_t* in, uint64_t n, const qlc_table* table,
+                               uint64_t* seg_bits, hipStream_t stream) {
+  hipLaunchKernelGGL(k_segment_bits, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), 0, stream,
+                     in, n, seg_log2(n), table, seg_bits);
   return hipGetLastError();
 }
 
