@@ -206,15 +206,30 @@ __device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uin
   const uint4* vin = reinterpret_cast<const uint4*>(in);
   const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
   uint64_t i = v0 + tid;
-  for (; i + 3 * nt < v1; i += 4 * nt) {
-    const uint4 a = vin[i];
-    const uint4 b = vin[i + nt];
-    const uint4 c = vin[i + 2 * nt];
-    const uint4 d = vin[i + 3 * nt];
-    hist_add_vec(sub, a, copy);
-    hist_add_vec(sub, b, copy);
-    hist_add_vec(sub, c, copy);
-    hist_add_vec(sub, d, copy);
+  if (i + 3 * nt < v1) {
+    // the next four vectors are loaded before the current four are counted
+    uint4 a = vin[i], b = vin[i + nt], c = vin[i + 2 * nt], d = vin[i + 3 * nt];
+    for (;;) {
+      const uint64_t nx = i + 4 * nt;
+      const bool more = nx + 3 * nt < v1;
+      uint4 na = a, nb = b, nc = c, nd = d;
+      if (more) {
+        na = vin[nx];
+        nb = vin[nx + nt];
+        nc = vin[nx + 2 * nt];
+        nd = vin[nx + 3 * nt];
+      }
+      hist_add_vec(sub, a, copy);
+      hist_add_vec(sub, b, copy);
+      hist_add_vec(sub, c, copy);
+      hist_add_vec(sub, d, copy);
+      i = nx;
+      if (!more) break;
+      a = na;
+      b = nb;
+      c = nc;
+      d = nd;
+    }
   }
   for (; i < v1; i += nt) hist_add_vec(sub, vin[i], copy);
   for (uint64_t j = (v1 << 4) + tid; j < seg1; j += nt)  // ragged tail of the input
