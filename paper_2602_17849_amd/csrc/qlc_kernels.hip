@@ -649,13 +649,14 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // register table (v_perm), the code is the window shifted right by it, and
 // three funnel shifts advance a 96-bit window by 3 + w_a bits.
 //
-// Memory: each lane streams its chunk in 64-byte superblocks (four 16-byte
-// bounds-checked buffer loads of one aligned 64-byte line segment) into a
-// private 2-superblock LDS ring (plus a mirror of the first words, so a
-// 4-word window never wraps), stored word-major so that window reads never
-// conflict on LDS banks.  A superblock is loaded at most once per 8-symbol
-// group; whole waves keep four register sets in rotation, so a superblock
-// is written to the ring four groups after its load was issued and every
+// Memory: each lane streams its chunk in 32-byte superblocks (two 16-byte
+// bounds-checked buffer loads) into a private 4-superblock LDS ring (plus a
+// mirror of the first words, so a 4-word window never wraps), stored
+// word-major so that window reads never conflict on LDS banks.  A
+// superblock is requested three superblocks ahead of the window, at most
+// one per 8-symbol group; whole waves keep four register sets in rotation,
+// so a superblock is written to the ring four groups after its load was
+// issued (at least six groups before the window can reach it) and every
 // wave waits at fixed program points for loads that old.  Lanes that need
 // no superblock issue the loads with an out-of-range offset (zeros
 // returned, no memory touched).  Decoded bytes are staged per lane in LDS
@@ -664,8 +665,9 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
 // 128-byte lines).
 // ===========================================================================
 constexpr int kDecLanes = kDecThreads;     // chunks per workgroup
-constexpr int kRingWords = 36;             // 2 x 16 ring words + 4 mirror words
-constexpr uint32_t kLookaheadBits = 512;
+constexpr int kRingWords = 36;             // 4 x 8 ring words + 4 mirror words
+constexpr uint32_t kSbLog2Bits = 8;         // superblock: 256 bits = 32 bytes
+constexpr uint32_t kLookaheadBits = 768;   // request a superblock three ahead
 constexpr uint32_t kOobOffset = 0xFFFFFFC0u;
 constexpr uint32_t kAreaSel = 0x01818180u;  // alignbit(kAreaSel, A, 29) = (A >> 29) | 0x0C0C0C00
 
@@ -683,7 +685,7 @@ __device__ __forceinline__ uint32_t stage_slot(uint32_t g, uint32_t t) {
 }
 
 struct Superblock {
-  uint4 q0, q1, q2, q3;
+  uint4 q0, q1;
 };
 
 __device__ __forceinline__ uint4 bufload16(__amdgpu_buffer_rsrc_t rsrc, uint32_t off) {
@@ -695,12 +697,10 @@ __device__ __forceinline__ Superblock load_sb(__amdgpu_buffer_rsrc_t rsrc, uint3
   Superblock s;
   s.q0 = bufload16(rsrc, off);
   s.q1 = bufload16(rsrc, off + 16);
-  s.q2 = bufload16(rsrc, off + 32);
-  s.q3 = bufload16(rsrc, off + 48);
   return s;
 }
 
-// Superblock `sb` (absolute number) into ring slot sb & 1 (words 16*(sb&1)),
+// Superblock `sb` (absolute number) into ring slot sb & 3 (words 8*(sb&3)),
 // in memory byte order (the window reads swap to most-significant-first);
 // slot 0's first four words are mirrored to words 32..35 so that a 4-word
 // window never wraps.
@@ -709,12 +709,11 @@ __device__ __forceinline__ Superblock load_sb(__amdgpu_buffer_rsrc_t rsrc, uint3
 // and the window reads of a wave are free of bank conflicts whatever the
 // lanes' positions.
 __device__ __forceinline__ void ring_put(uint32_t* ring, uint32_t sb, const Superblock& s) {
-  uint32_t* r = ring + (sb & 1u) * 16u * kDecLanes;
-  const uint32_t v[16] = {s.q0.x, s.q0.y, s.q0.z, s.q0.w, s.q1.x, s.q1.y, s.q1.z, s.q1.w,
-                          s.q2.x, s.q2.y, s.q2.z, s.q2.w, s.q3.x, s.q3.y, s.q3.z, s.q3.w};
+  uint32_t* r = ring + (sb & 3u) * 8u * kDecLanes;
+  const uint32_t v[8] = {s.q0.x, s.q0.y, s.q0.z, s.q0.w, s.q1.x, s.q1.y, s.q1.z, s.q1.w};
 #pragma unroll
-  for (int i = 0; i < 16; ++i) r[i * kDecLanes] = v[i];
-  if ((sb & 1u) == 0) {
+  for (int i = 0; i < 8; ++i) r[i * kDecLanes] = v[i];
+  if ((sb & 3u) == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) ring[(32 + i) * kDecLanes] = v[i];
   }
@@ -837,15 +836,15 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
   bool bad = false;
 
   if (j_wave < nchunks) {
-    // Buffer resource rebased at the wave's first chunk (64-byte aligned):
+    // Buffer resource rebased at the wave's first superblock (32-byte aligned):
     // loads past the end of the stream, or through a corrupt index, return
     // zeros.
     const uint64_t stream_bytes = ((total + 31) >> 5) << 2;
     const uint64_t wave_bit = index[j_wave];
     const uint64_t base_sb =
-        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 9)) |
-        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> 41)) << 32);
-    const uint64_t base_byte = base_sb << 6;
+        (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> kSbLog2Bits)) |
+        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(wave_bit >> (32 + kSbLog2Bits))) << 32);
+    const uint64_t base_byte = base_sb << (kSbLog2Bits - 3);
     uint64_t avail = stream_bytes > base_byte ? stream_bytes - base_byte : 0;
     if (avail > kOobOffset) avail = kOobOffset;
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -863,7 +862,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       const uint64_t left = n - (j << log2_chunk);
       const uint32_t nsym = (uint32_t)(left < C ? left : C);
       if (pos0 > end || end > total || (j == 0 && pos0 != 0) || pos0 < wave_bit ||
-          ((pos0 >> 9) - base_sb) > (kOobOffset >> 6) - 1024) {
+          ((pos0 >> kSbLog2Bits) - base_sb) > (kOobOffset >> (kSbLog2Bits - 3)) - 4096) {
         bad = true;
       } else {
         my_groups = nsym >> 3;
@@ -878,15 +877,20 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     L.sh_hi = sh_hi;
     L.errbits = 0;
     const uint32_t sb0 = (uint32_t)base_sb;         // ring slots follow absolute superblocks
-    uint32_t fsb = live ? (uint32_t)((pos0 >> 9) - base_sb) : 0;  // next superblock (wave-relative)
+    uint32_t fsb = live ? (uint32_t)((pos0 >> kSbLog2Bits) - base_sb) : 0;  // next superblock (wave-relative)
     {
-      const Superblock p0 = load_sb(rsrc, live ? (fsb << 6) : kOobOffset);
-      const Superblock p1 = load_sb(rsrc, live ? ((fsb + 1) << 6) : kOobOffset);
+      constexpr uint32_t kSh = kSbLog2Bits - 3;
+      const Superblock p0 = load_sb(rsrc, live ? (fsb << kSh) : kOobOffset);
+      const Superblock p1 = load_sb(rsrc, live ? ((fsb + 1) << kSh) : kOobOffset);
+      const Superblock p2 = load_sb(rsrc, live ? ((fsb + 2) << kSh) : kOobOffset);
+      const Superblock p3 = load_sb(rsrc, live ? ((fsb + 3) << kSh) : kOobOffset);
       ring_put(L.ring, sb0 + fsb, p0);
       ring_put(L.ring, sb0 + fsb + 1, p1);
-      fsb += 2;
+      ring_put(L.ring, sb0 + fsb + 2, p2);
+      ring_put(L.ring, sb0 + fsb + 3, p3);
+      fsb += 4;
     }
-    const uint64_t rel0 = base_sb << 9;
+    const uint64_t rel0 = base_sb << kSbLog2Bits;
     Superblock pa, pb;
     uint32_t sba = 0, sbb = 0;
     bool va = false, vb = false;
@@ -898,9 +902,9 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
 #define QLC_DEC_REFILL(VAL, SBX, PX)                                                    \
   {                                                                                     \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
-    VAL = ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
+    VAL = ((uint64_t)fsb << kSbLog2Bits) < (L.pm1 + 1 - rel0) + kLookaheadBits;         \
     SBX = fsb;                                                                          \
-    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
     fsb += VAL ? 1u : 0u;                                                               \
   }
 #define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
@@ -909,9 +913,9 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     if (gg < my_groups) stage[stage_slot(gg, tid)] = decode_group(L, S.lut);            \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
     VAL = live && gg < my_groups &&                                                     \
-          ((uint64_t)fsb << 9) < (L.pm1 + 1 - rel0) + kLookaheadBits;                   \
+          ((uint64_t)fsb << kSbLog2Bits) < (L.pm1 + 1 - rel0) + kLookaheadBits;         \
     SBX = fsb;                                                                          \
-    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
     fsb += VAL ? 1u : 0u;                                                               \
   }
 
@@ -937,17 +941,17 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       uint32_t q = (uint32_t)(L.pm1 - rel0);
       const uint32_t endr = (uint32_t)(end - rel0);  // no superblock past the chunk's end
       const uint32_t* ring = L.ring;
-      const uint32_t rs = (uint32_t)base_sb & 1u;  // ring slot parity of relative superblocks
-      Window W = window_read(ring, q + (rs << 9));
+      const uint32_t rs = (uint32_t)base_sb & 3u;  // ring slot of relative superblock 0
+      Window W = window_read(ring, q + (rs << kSbLog2Bits));
 #define QLC_DEC_UNIT(GI, VAL, SBX, PX)                                                  \
   {                                                                                     \
     uint32_t e[8];                                                                      \
     q += decode_chain(W, q, L.sh_lo, L.sh_hi, S.lut, e);                                \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
-    W = window_read(ring, q + (rs << 9));                                               \
-    VAL = (fsb << 9) < min(q + 1 + kLookaheadBits, endr);                               \
+    W = window_read(ring, q + (rs << kSbLog2Bits));                                     \
+    VAL = (fsb << kSbLog2Bits) < min(q + 1 + kLookaheadBits, endr);                     \
     SBX = fsb;                                                                          \
-    PX = load_sb(rsrc, VAL ? (fsb << 6) : kOobOffset);                                  \
+    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
     fsb += VAL ? 1u : 0u;                                                               \
     stage[stage_slot((GI), tid)] = pack_group(e, L.errbits);                            \
   }
