@@ -955,23 +955,26 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     fsb += VAL ? 1u : 0u;                                                               \
     stage[stage_slot((GI), tid)] = pack_group(e, L.errbits);                            \
   }
+      // One iteration = R groups and their flush, so that the flush sits at
+      // a fixed program point: the waits for loads issued before it then
+      // need not wait for its stores as well.
 #pragma unroll 1
-      for (uint32_t g = 0; g < wave_groups; g += 4) {
-        QLC_DEC_UNIT(g + 0, va, sba, pa)
-        QLC_DEC_UNIT(g + 1, vb, sbb, pb)
-        QLC_DEC_UNIT(g + 2, vc, sbc, pc_)
-        QLC_DEC_UNIT(g + 3, vd, sbd, pd_)
-        if ((g & (R - 1)) == R - 4) {
-          const uint32_t g0 = g + 4 - R;
-          __builtin_amdgcn_wave_barrier();
+      for (uint32_t g0 = 0; g0 < wave_groups; g0 += R) {
 #pragma unroll
-          for (uint32_t k = 0; k < R; ++k) {
-            const uint32_t stid = (tid & ~63u) | (lane / R + kRuns * k);
-            const uint2 v = S.stage[stid * R + stage_slot(g0 + part, stid)];
-            *reinterpret_cast<uint2*>(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8) = v;
-          }
-          __builtin_amdgcn_wave_barrier();
+        for (uint32_t u = 0; u < R; u += 4) {
+          QLC_DEC_UNIT(g0 + u + 0, va, sba, pa)
+          QLC_DEC_UNIT(g0 + u + 1, vb, sbb, pb)
+          QLC_DEC_UNIT(g0 + u + 2, vc, sbc, pc_)
+          QLC_DEC_UNIT(g0 + u + 3, vd, sbd, pd_)
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (uint32_t k = 0; k < R; ++k) {
+          const uint32_t stid = (tid & ~63u) | (lane / R + kRuns * k);
+          const uint2 v = S.stage[stid * R + stage_slot(g0 + part, stid)];
+          *reinterpret_cast<uint2*>(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8) = v;
+        }
+        __builtin_amdgcn_wave_barrier();
       }
 #undef QLC_DEC_UNIT
       L.pm1 = rel0 + q;
