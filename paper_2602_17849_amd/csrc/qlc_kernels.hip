@@ -354,6 +354,144 @@ struct Packer {
   }
 };
 
+// State of a segment's encode carried from tile to tile.
+struct EncSeg {
+  const uint8_t* in;
+  uint64_t seg1;
+  uint64_t R;                        // global bit offset of the current tile
+  uint64_t seg_w0;                   // the segment's first stream word
+  uint64_t cap_words;
+  uint64_t cmask;                    // chunk_symbols - 1
+  uint32_t log2_chunk;
+  bool last_seg;
+  __amdgpu_buffer_rsrc_t out_rsrc;   // stream words from seg_w0 on, clipped at cap_words
+  uint64_t* index_out;
+  uint4 nx0, nx1;                    // the next full tile's input (prefetched)
+};
+
+// One tile of 8192 symbols at t0 (kFull: a whole tile; else the input's
+// ragged last tile [t0, seg1)).  Thread tid owns two runs of the tile:
+// symbols 16*tid.. (first half) and 4096+16*tid.. (second half), so that
+// its loads are coalesced; every first-half run precedes every second-half
+// run in the stream, and one block scan of the packed pair of run lengths
+// (b0 | b1 << 16) places both (run bits <= 176, block totals < 2^16).
+// Returns true in a thread one of whose stores would have passed cap_words.
+template <bool kFull>
+__device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, uint32_t tid) {
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  bool cap = false;
+  uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (whole tiles)
+  uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
+  if (kFull) {
+    const uint4 v0 = E.nx0, v1 = E.nx1;
+    {  // prefetch the next tile (this one again when no whole tile follows)
+      const uint64_t nt = (t0 + 2 * kEncTile <= E.seg1) ? t0 + kEncTile : t0;
+      const uint4* p = reinterpret_cast<const uint4*>(E.in + nt + (uint64_t)tid * 16);
+      E.nx0 = p[0];
+      E.nx1 = p[kEncThreads];
+    }
+    const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t w = sw[k >> 1];
+      const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
+      const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
+      const uint32_t l1 = e1 >> 16;
+      pc[k] = ((e0 & 0xFFFFu) << l1) | (e1 & 0xFFFFu);
+      pl[k] = (e0 >> 16) + l1;
+      if (k < 8) b0 += pl[k];
+      else b1 += pl[k];
+    }
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < 32; ++k) {
+      const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+      const uint32_t l = i < E.seg1 ? (S.lut[E.in[i]] >> 16) : 0u;
+      if (k < 16) b0 += l;
+      else b1 += l;
+    }
+  }
+  const uint32_t packed = b0 | (b1 << 16);
+  const uint32_t incl = wave_inclusive_scan_u32(packed);
+  if (lane == 63) S.wave_sum[wave] = incl;
+  __syncthreads();
+  uint32_t o = 0, h = 0;
+#pragma unroll
+  for (int w = 0; w < kEncThreads / 64; ++w) {
+    const uint32_t ws = S.wave_sum[w];
+    o += (w < (int)wave) ? ws : 0u;
+    h += ws;
+  }
+  const uint32_t h0 = h & 0xFFFFu, h1 = h >> 16;
+  const uint32_t tile_bits = h0 + h1;
+  const uint32_t g = (uint32_t)(E.R & 31);
+  const uint32_t off0 = (o & 0xFFFFu) + (incl & 0xFFFFu) - b0;
+  const uint32_t off1 = h0 + (o >> 16) + (incl >> 16) - b1;
+  {
+    Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
+    Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
+    if (kFull) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
+#pragma unroll
+      for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
+    } else {
+#pragma unroll 1
+      for (int k = 0; k < 32; ++k) {
+        const uint64_t i =
+            t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
+        if (i < E.seg1) {
+          const uint32_t e = S.lut[E.in[i]];
+          if (k < 16) P0.put(S.words, e & 0xFFFFu, e >> 16);
+          else P1.put(S.words, e & 0xFFFFu, e >> 16);
+        }
+      }
+    }
+    P0.finish(S.words);
+    P1.finish(S.words);
+    // chunk index entries: a run's first symbol may start a chunk
+    const uint64_t i0s = t0 + (uint64_t)tid * 16;
+    const uint64_t i1s = i0s + kEncTile / 2;
+    if (i0s < E.seg1 && (i0s & E.cmask) == 0) E.index_out[i0s >> E.log2_chunk] = E.R + off0;
+    if (i1s < E.seg1 && (i1s & E.cmask) == 0) E.index_out[i1s >> E.log2_chunk] = E.R + off1;
+  }
+  __syncthreads();
+  // store the whole words (and, at the very end, the padded last word),
+  // clearing them for the next tile
+  const uint32_t endb = g + tile_bits;
+  const bool final_tile = E.last_seg && (t0 + kEncTile >= E.seg1);
+  const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
+  const uint32_t wr = (uint32_t)((E.R >> 5) - E.seg_w0);  // tile's first word, segment-relative
+  if (tid == 0 && (E.R >> 5) + nw > E.cap_words) cap = true;
+  // four words per thread per store; the buffer resource drops anything
+  // past the capacity
+  for (uint32_t i = 4 * tid; i < nw; i += 4 * kEncThreads) {
+    uint4* src = reinterpret_cast<uint4*>(&S.words[i]);
+    if (i + 4 <= nw) {
+      const uint4 v = *src;
+      *src = make_uint4(0, 0, 0, 0);
+      const v4u32 ov = {__builtin_bswap32(v.x), __builtin_bswap32(v.y), __builtin_bswap32(v.z),
+                        __builtin_bswap32(v.w)};
+      __builtin_amdgcn_raw_buffer_store_b128(ov, E.out_rsrc, (wr + i) * 4, 0, 0);
+    } else {
+      for (uint32_t k = i; k < nw; ++k) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bswap32(S.words[k]), E.out_rsrc,
+                                              (wr + k) * 4, 0, 0);
+        S.words[k] = 0;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && !final_tile) {
+    // the partial last word becomes word 0 of the next tile
+    const uint32_t carry = S.words[endb >> 5];
+    S.words[endb >> 5] = 0;
+    S.words[0] = carry;
+  }
+  E.R += tile_bits;
+  return cap;
+}
+
 // Encode symbols [seg0, seg1) of `in`, whose first code starts at stream
 // bit G (kEncThreads threads, tid = threadIdx.x).  On entry S.lut holds the encoder LUT and
 // S.words[1..] are zero; on return S.words[1..] are zero again.  Every
@@ -361,12 +499,12 @@ struct Packer {
 // carries the previous segment's last bits (recomputed from the 16 symbols
 // before seg0); its partial last word is left to the next segment, unless
 // `last_seg` (padded and stored).  Returns true in a thread one of whose
-// stores would have passed cap_words (that store is dropped).
+// stores would have passed cap_words (that store is dropped).  Whole tiles
+// run in a loop of their own, the ragged last tile (if any) after it.
 __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, uint64_t seg0, uint64_t seg1,
                                uint64_t G, bool last_seg, uint32_t log2_chunk,
                                uint32_t* __restrict__ bits_out, uint64_t cap_words,
                                uint64_t* __restrict__ index_out, EncSmem& S, uint32_t tid) {
-  const uint32_t lane = tid & 63, wave = tid >> 6;
   bool cap = false;
   // ---- last bits of the previous segment (recomputed from its input) ----
   if (tid == 0) {
@@ -381,140 +519,33 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
     }
     S.words[0] = w0;
   }
-  uint64_t R = G;  // global bit offset of the current tile
+  EncSeg E;
+  E.in = in;
+  E.seg1 = seg1;
+  E.R = G;
+  E.cap_words = cap_words;
+  E.cmask = (1ull << log2_chunk) - 1;
+  E.log2_chunk = log2_chunk;
+  E.last_seg = last_seg;
+  E.index_out = index_out;
   // Output through a buffer resource based at the segment's first word
   // (segment-relative offsets stay far below 2^32): stores at or past
   // cap_words are dropped by the hardware.
-  const uint64_t seg_w0 = G >> 5;
-  const uint64_t room = cap_words > seg_w0 ? (cap_words - seg_w0) * 4 : 0;
-  const __amdgpu_buffer_rsrc_t out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-      bits_out + (cap_words > seg_w0 ? seg_w0 : 0), (short)0,
+  E.seg_w0 = G >> 5;
+  const uint64_t room = cap_words > E.seg_w0 ? (cap_words - E.seg_w0) * 4 : 0;
+  E.out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      bits_out + (cap_words > E.seg_w0 ? E.seg_w0 : 0), (short)0,
       (int)(uint32_t)(room < 0xFFFFFFF0ull ? room : 0xFFFFFFF0ull), 0x00020000);
-  const uint64_t cmask = (1ull << log2_chunk) - 1;
-  uint4 nx0 = make_uint4(0, 0, 0, 0), nx1 = nx0;
+  E.nx0 = make_uint4(0, 0, 0, 0);
+  E.nx1 = E.nx0;
   if (seg0 + kEncTile <= seg1) {
     const uint4* p = reinterpret_cast<const uint4*>(in + seg0 + (uint64_t)tid * 16);
-    nx0 = p[0];
-    nx1 = p[kEncThreads];
+    E.nx0 = p[0];
+    E.nx1 = p[kEncThreads];
   }
-  for (uint64_t t0 = seg0;; t0 += kEncTile) {
-    const bool full = t0 + kEncTile <= seg1;
-    uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (full tiles)
-    uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
-    if (full) {
-      const uint4 v0 = nx0, v1 = nx1;
-      if (t0 + 2 * kEncTile <= seg1) {  // prefetch the next tile
-        const uint4* p = reinterpret_cast<const uint4*>(in + t0 + kEncTile + (uint64_t)tid * 16);
-        nx0 = p[0];
-        nx1 = p[kEncThreads];
-      }
-      const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t w = sw[k >> 1];
-        const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
-        const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
-        const uint32_t l1 = e1 >> 16;
-        pc[k] = ((e0 & 0xFFFFu) << l1) | (e1 & 0xFFFFu);
-        pl[k] = (e0 >> 16) + l1;
-        if (k < 8) b0 += pl[k];
-        else b1 += pl[k];
-      }
-    } else {
-      // the input's ragged last tile: symbols [t0, seg1)
-#pragma unroll 1
-      for (int k = 0; k < 32; ++k) {
-        const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-        const uint32_t l = i < seg1 ? (S.lut[in[i]] >> 16) : 0u;
-        if (k < 16) b0 += l;
-        else b1 += l;
-      }
-    }
-    // Thread tid owns two runs of the tile: symbols 16*tid.. (first half)
-    // and 4096+16*tid.. (second half), so that its loads are coalesced.
-    // Every first-half run precedes every second-half run in the stream;
-    // one block scan of the packed pair (b0 | b1 << 16) places both
-    // (run bits <= 176, block totals < 2^16).
-    const uint32_t packed = b0 | (b1 << 16);
-    const uint32_t incl = wave_inclusive_scan_u32(packed);
-    if (lane == 63) S.wave_sum[wave] = incl;
-    __syncthreads();
-    uint32_t o = 0, h = 0;
-#pragma unroll
-    for (int w = 0; w < kEncThreads / 64; ++w) {
-      const uint32_t ws = S.wave_sum[w];
-      o += (w < (int)wave) ? ws : 0u;
-      h += ws;
-    }
-    const uint32_t h0 = h & 0xFFFFu, h1 = h >> 16;
-    const uint32_t tile_bits = h0 + h1;
-    const uint32_t g = (uint32_t)(R & 31);
-    const uint32_t off0 = (o & 0xFFFFu) + (incl & 0xFFFFu) - b0;
-    const uint32_t off1 = h0 + (o >> 16) + (incl >> 16) - b1;
-    {
-      Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
-      Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
-      if (full) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
-#pragma unroll
-        for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
-      } else {
-#pragma unroll 1
-        for (int k = 0; k < 32; ++k) {
-          const uint64_t i =
-              t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-          if (i < seg1) {
-            const uint32_t e = S.lut[in[i]];
-            if (k < 16) P0.put(S.words, e & 0xFFFFu, e >> 16);
-            else P1.put(S.words, e & 0xFFFFu, e >> 16);
-          }
-        }
-      }
-      P0.finish(S.words);
-      P1.finish(S.words);
-      // chunk index entries: a run's first symbol may start a chunk
-      const uint64_t i0s = t0 + (uint64_t)tid * 16;
-      const uint64_t i1s = i0s + kEncTile / 2;
-      if (i0s < seg1 && (i0s & cmask) == 0) index_out[i0s >> log2_chunk] = R + off0;
-      if (i1s < seg1 && (i1s & cmask) == 0) index_out[i1s >> log2_chunk] = R + off1;
-    }
-    __syncthreads();
-    // store the whole words (and, at the very end, the padded last word),
-    // clearing them for the next tile
-    const uint32_t endb = g + tile_bits;
-    const bool final_tile = last_seg && (t0 + kEncTile >= seg1);
-    const uint32_t nw = final_tile ? (endb + 31) >> 5 : endb >> 5;
-    const uint32_t wr = (uint32_t)((R >> 5) - seg_w0);  // tile's first word, segment-relative
-    if (tid == 0 && (R >> 5) + nw > cap_words) cap = true;
-    // four words per thread per store; the buffer resource drops anything
-    // past the capacity
-    for (uint32_t i = 4 * tid; i < nw; i += 4 * kEncThreads) {
-      uint4* src = reinterpret_cast<uint4*>(&S.words[i]);
-      if (i + 4 <= nw) {
-        const uint4 v = *src;
-        *src = make_uint4(0, 0, 0, 0);
-        const v4u32 o = {__builtin_bswap32(v.x), __builtin_bswap32(v.y), __builtin_bswap32(v.z),
-                         __builtin_bswap32(v.w)};
-        __builtin_amdgcn_raw_buffer_store_b128(o, out_rsrc, (wr + i) * 4, 0, 0);
-      } else {
-        for (uint32_t k = i; k < nw; ++k) {
-          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bswap32(S.words[k]), out_rsrc,
-                                                (wr + k) * 4, 0, 0);
-          S.words[k] = 0;
-        }
-      }
-    }
-    __syncthreads();
-    if (tid == 0 && !final_tile) {
-      // the partial last word becomes word 0 of the next tile
-      const uint32_t carry = S.words[endb >> 5];
-      S.words[endb >> 5] = 0;
-      S.words[0] = carry;
-    }
-    R += tile_bits;
-    if (t0 + kEncTile >= seg1) break;
-  }
+  uint64_t t0 = seg0;
+  for (; t0 + kEncTile <= seg1; t0 += kEncTile) cap |= encode_tile<true>(E, t0, S, tid);
+  if (t0 < seg1 || seg0 == seg1) cap |= encode_tile<false>(E, t0, S, tid);
   return cap;
 }
 
