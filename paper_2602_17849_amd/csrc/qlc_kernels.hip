@@ -354,6 +354,24 @@ struct Packer {
   }
 };
 
+// Code pair of two encoder LUT entries (code | length << 16): code0 << len1
+// | code1, and its length.  Written with SDWA word selects (one operation
+// each) because the compiler otherwise extracts the halves separately.
+__device__ __forceinline__ uint32_t pair_code(uint32_t e0, uint32_t e1) {
+  uint32_t t, r;
+  asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_0"
+      : "=v"(t) : "v"(e1), "v"(e0));
+  asm("v_or_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+      : "=v"(r) : "v"(t), "v"(e1));
+  return r;
+}
+__device__ __forceinline__ uint32_t pair_len(uint32_t e0, uint32_t e1) {
+  uint32_t r;
+  asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 src1_sel:WORD_1"
+      : "=v"(r) : "v"(e0), "v"(e1));
+  return r;
+}
+
 // State of a segment's encode carried from tile to tile.
 struct EncSeg {
   const uint8_t* in;
@@ -396,9 +414,8 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
       const uint32_t w = sw[k >> 1];
       const uint32_t e0 = S.lut[(w >> (16 * (k & 1))) & 0xFFu];
       const uint32_t e1 = S.lut[(w >> (16 * (k & 1) + 8)) & 0xFFu];
-      const uint32_t l1 = e1 >> 16;
-      pc[k] = ((e0 & 0xFFFFu) << l1) | (e1 & 0xFFFFu);
-      pl[k] = (e0 >> 16) + l1;
+      pc[k] = pair_code(e0, e1);
+      pl[k] = pair_len(e0, e1);
       if (k < 8) b0 += pl[k];
       else b1 += pl[k];
     }
