@@ -143,29 +143,94 @@ def test_batched_repeated_calls_same_workspace():
         check_round_trip(b, xs)
 
 
-def test_batched_given_tables():
+def _give_oracle_tables(b, xs, mode=qlc.LAYOUT_PAPER_T1, which=None):
+    """Copy the oracle's table of each tensor (or of those in `which`) into
+    the batch; returns {i: oracle table}."""
+    ots = {}
+    for i, x in enumerate(xs):
+        if which is not None and i not in which:
+            continue
+        ot = oracle.build_table(oracle.histogram(x), mode)
+        ots[i] = ot
+        blob = bytes(ot.width.astype(np.uint8)) + bytes(ot.rank_to_sym.astype(np.uint8))
+        raw = qlc.qlc_table_deserialize(blob)
+        b.table(i).copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(DEV))
+    return ots
+
+
+# (log2_segment, lag_segments, workgroups, reserved); lag 1 lets a given-table
+# job's encode items follow its bit-count items one segment behind
+GIVEN_TUNINGS = [None, (13, 1, 0, 0), (16, 1, 0, 0), (13, 3, 7, 0), (13, 0, 0, 0)]
+
+
+@pytest.mark.parametrize("tuning", GIVEN_TUNINGS)
+def test_batched_given_tables(tuning):
     """build_table = 0: the caller's tables (here Table 1 layouts built by
     the oracle from each tensor's histogram) are used as given."""
     C = 4096
     b, xs = make_batch(SIZES, C, capacity="bound", build_table=False)
-    ots = []
-    for i, x in enumerate(xs):
-        ot = oracle.build_table(oracle.histogram(x), qlc.LAYOUT_PAPER_T1)
-        ots.append(ot)
-        blob = bytes(ot.width.astype(np.uint8)) + bytes(ot.rank_to_sym.astype(np.uint8))
-        raw = qlc.qlc_table_deserialize(blob)
-        b.table(i).copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(DEV))
-    ws = b.workspace()
-    b.encode(ws, qlc.LAYOUT_SEARCH_QUAD)   # mode is ignored by build_table = 0 jobs
+    ots = _give_oracle_tables(b, xs)
+    ws = b.workspace(tuning)
+    b.encode(ws, qlc.LAYOUT_SEARCH_QUAD, tuning)   # mode is ignored by build_table = 0 jobs
     torch.cuda.synchronize()
     for i, x in enumerate(xs):
         err, total, bits, index, _ = result(b, i)
         st, obits, oindex, ototal = oracle.encode(x, ots[i], C)
         assert err == 0 and total == ototal
         assert np.array_equal(bits, obits) and np.array_equal(index, oindex), i
-    b.decode(ws)
+    b.decode(ws, tuning)
     torch.cuda.synchronize()
     check_round_trip(b, xs)
+
+
+def test_batched_mixed_given_and_built_tables():
+    """Jobs that build their table and jobs with a given table in one call,
+    at the smallest lag: both kinds match the oracle."""
+    C = 2048
+    tuning = (13, 1, 0, 0)
+    b, xs = make_batch(SIZES, C, capacity="bound", build_table=True)
+    given = {i for i in range(len(SIZES)) if i % 2}
+    ots = _give_oracle_tables(b, xs, qlc.LAYOUT_PAPER_T2, given)
+    for i in given:
+        b.jobs_host[i].build_table = 0
+    b.upload_jobs()
+    ws = b.workspace(tuning)
+    b.encode(ws, qlc.LAYOUT_SEARCH_QUAD, tuning)
+    torch.cuda.synchronize()
+    for i, x in enumerate(xs):
+        err, total, bits, index, table = result(b, i)
+        ot = ots[i] if i in given else oracle.build_table(oracle.histogram(x),
+                                                          qlc.LAYOUT_SEARCH_QUAD)
+        st, obits, oindex, ototal = oracle.encode(x, ot, C)
+        assert err == 0 and total == ototal, i
+        assert np.array_equal(bits, obits) and np.array_equal(index, oindex), i
+    b.decode(ws, tuning)
+    torch.cuda.synchronize()
+    check_round_trip(b, xs)
+
+
+def test_batched_one_large_given_table_job_matches_plain():
+    """A single large tensor with a given table through the batched form at
+    lag 1 (encode items one segment behind the bit counts) equals qlc_encode."""
+    n, C = 9 * (1 << 20) + 4096 + 48, 2048
+    x = datagen.laplace_outlier_rows(1, (n + 31) // 32 * 32, 11)[:n].contiguous()
+    xd = x.to(DEV)
+    t = qlc.new_table()
+    ws1 = qlc.new_workspace(n, C)
+    qlc.qlc_build_table(xd, qlc.LAYOUT_SEARCH_QUAD, t, ws1)
+    ref = qlc.compress(xd, chunk_symbols=C)       # builds the same table itself
+    b = qlc.Batch([n], chunk_symbols=C, device=DEV, capacity="bound", build_table=False)
+    b.input(0).copy_(xd)
+    b.table(0).copy_(t)
+    for tuning in [(16, 1, 0, 0), (18, 1, 0, 0), (14, 2, 5, 0)]:
+        b.bits.zero_()
+        ws = b.workspace(tuning)
+        b.encode(ws, qlc.LAYOUT_SEARCH_QUAD, tuning)
+        torch.cuda.synchronize()
+        err, total, bits, index, table = result(b, 0)
+        assert err == 0 and total == ref.total_bits(), tuning
+        assert np.array_equal(bits, ref.bits[:ref.nbytes()].cpu().numpy()), tuning
+        assert np.array_equal(index, ref.index[:qlc.qlc_chunk_count(n, C)].cpu().numpy()), tuning
 
 
 def test_batched_errors_stay_per_job():
