@@ -126,6 +126,16 @@ qlc_status qlc_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream);
 qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out,
                          void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Step 1 for a table shared by many tensors (Implementation section: one
+ * LUT per tensor type, obtained a priori): hist_inout[s] += number of
+ * bytes of `in` equal to s.  hist_inout (256 uint64 counts, device, 8-byte
+ * aligned) is read and written by the last workgroup on `stream`, so calls
+ * on one stream accumulate in order; the caller zeroes it before the first
+ * call.  Same argument rules and errors as qlc_histogram.  Feeding the sum
+ * to qlc_table_from_histogram gives one table for every tensor summed. */
+qlc_status qlc_histogram_accumulate(const uint8_t* in, uint64_t n, uint64_t* hist_inout,
+                                    void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Steps 2-4 (Implementation section, Tables 1-4): build *table_out from a
  * device histogram of 256 uint64 counts. */
 qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,

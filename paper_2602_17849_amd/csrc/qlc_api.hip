@@ -162,6 +162,16 @@ qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out, void
                                      0, nullptr, stream));
 }
 
+qlc_status qlc_histogram_accumulate(const uint8_t* in, uint64_t n, uint64_t* hist_inout, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+  if ((n && !in) || !hist_inout || !ws || n >= QLC_MAX_SYMBOLS_PER_CALL) return QLC_ERR_INVALID_ARGUMENT;
+  if (!aligned(in, 16) || !aligned(hist_inout, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < ws_bytes_for(n)) return QLC_ERR_INVALID_ARGUMENT;
+  WsView v = carve(ws, n);
+  return hip_status(launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, hist_inout,
+                                     kHistGlobal | kHistAccumulate, 0, nullptr, stream));
+}
+
 qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
                                     qlc_table* table_out, hipStream_t stream) {
   if (!hist || !table_out || (uint32_t)mode > QLC_LAYOUT_PAPER_T2) return QLC_ERR_INVALID_ARGUMENT;

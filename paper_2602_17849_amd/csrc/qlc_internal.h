@@ -31,6 +31,7 @@ constexpr int kNumXcd = 8;            // MI355X: 8 accelerator complex dies
 constexpr uint32_t kHistSegment = 1;     // write each segment's histogram
 constexpr uint32_t kHistGlobal = 2;      // fold the whole input's histogram
 constexpr uint32_t kHistBuildTable = 4;  // ... and build the table from it
+constexpr uint32_t kHistAccumulate = 8;  // add the whole input's histogram to hist_out
 
 // ---- epoch-tagged cross-workgroup words -----------------------------------
 // [63] valid, [61:40] launch epoch (22 bits), [39:0] value

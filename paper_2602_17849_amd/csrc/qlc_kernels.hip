@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
     uint64_t s = 0;
 #pragma unroll
     for (int x = 0; x < kNumXcd; ++x) s += load_relaxed_u64(&xcd_part[x * 256 + tid]);
-    if (hist_out) hist_out[tid] = s;
+    if (hist_out) hist_out[tid] = (flags & kHistAccumulate) ? hist_out[tid] + s : s;
     hsum[tid] = s;
 #pragma unroll
     for (int x = 0; x < kNumXcd; ++x) store_relaxed_u64(&xcd_part[x * 256 + tid], 0);

@@ -103,6 +103,7 @@ _SIGNATURES = {
     "qlc_workspace_bytes": ([_u64, _u32], _sz),
     "qlc_workspace_init": ([_vp, _sz, _vp], ctypes.c_int),
     "qlc_histogram": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_histogram_accumulate": ([_vp, _u64, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_table_from_histogram": ([_vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
     "qlc_build_table": ([_vp, _u64, ctypes.c_int, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_encode": ([_vp, _u64, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -183,6 +184,27 @@ def qlc_workspace_init(ws: torch.Tensor, stream=None):
 def qlc_histogram(x: torch.Tensor, hist_out: torch.Tensor, ws: torch.Tensor, stream=None):
     _check(lib().qlc_histogram(_p(x), x.numel(), _p(hist_out), _p(ws), _nbytes(ws),
                                _stream(stream)), "qlc_histogram")
+
+
+def qlc_histogram_accumulate(x: torch.Tensor, hist_inout: torch.Tensor, ws: torch.Tensor,
+                             stream=None):
+    _check(lib().qlc_histogram_accumulate(_p(x), x.numel(), _p(hist_inout), _p(ws), _nbytes(ws),
+                                          _stream(stream)), "qlc_histogram_accumulate")
+
+
+def shared_table(xs, mode: int = LAYOUT_SEARCH_QUAD, stream=None) -> torch.Tensor:
+    """One table for all device tensors in `xs` (a tensor type's LUT built
+    a priori): their histograms summed on the device, then steps 2-4."""
+    xs = list(xs)
+    dev = xs[0].device if xs else torch.device("cuda")
+    hist = torch.zeros(256, dtype=torch.int64, device=dev)
+    ws = torch.zeros(max([qlc_workspace_bytes(x.numel()) for x in xs] + [256]),
+                     dtype=torch.uint8, device=dev)
+    for x in xs:
+        qlc_histogram_accumulate(x, hist, ws, stream)
+    table = new_table(dev)
+    qlc_table_from_histogram(hist, mode, table, stream)
+    return table
 
 
 def qlc_table_from_histogram(hist: torch.Tensor, mode: int, table_out: torch.Tensor, stream=None):

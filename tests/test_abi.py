@@ -56,6 +56,10 @@ def test_argument_errors_are_synchronous():
     assert L.qlc_encode(ws, 10, ws, 4096, ws, 64, ws, ws, ws, ws, 16, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_build_table(ws, 10, 9, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_histogram(0, 10, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_histogram_accumulate(0, 10, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_histogram_accumulate(ws, 10, ws + 4, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_histogram_accumulate(ws, 10, 0, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_histogram_accumulate(ws, 1 << 20, ws, ws, 16, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_decode(ws, 0, ws, 4096, ws, 10, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_encode(ws, 1 << 36, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
 

@@ -37,6 +37,32 @@ def test_histogram(n):
         assert np.array_equal(h.cpu().numpy().astype(np.uint64), oracle.histogram(x)), name
 
 
+def test_histogram_accumulate_and_shared_table():
+    """Histograms summed over several tensors on the device equal the
+    oracle's histogram of their concatenation; the table built from the sum
+    (one LUT for the tensor type) equals the oracle's, and encoding each
+    tensor with it equals the oracle's encode with that table."""
+    xs = [x for n in (0, 17, 4097, 100003, 262144 + 77) for _, x in _inputs(n, seed=3)]
+    h = torch.zeros(256, dtype=torch.int64, device=DEV)
+    h[:] = 5                                        # accumulation adds to what is there
+    ws = qlc.new_workspace(max(x.size for x in xs))
+    for x in xs:
+        qlc.qlc_histogram_accumulate(to_dev(x), h, ws)
+    torch.cuda.synchronize()
+    ref = oracle.histogram(np.concatenate(xs)) + np.uint64(5)
+    assert np.array_equal(h.cpu().numpy().astype(np.uint64), ref)
+    for mode in (qlc.LAYOUT_SEARCH_QUAD, qlc.LAYOUT_PAPER_T1):
+        t = qlc.shared_table([to_dev(x) for x in xs], mode)
+        torch.cuda.synchronize()
+        ot = oracle.build_table(oracle.histogram(np.concatenate(xs)), mode)
+        assert_table_equal(t, ot)
+        for x in xs[::3]:
+            err, bits, nb, index, total = gpu_encode(to_dev(x), t, 4096)
+            st, obits, oindex, ototal = oracle.encode(x, ot, 4096)
+            assert err == 0 and total == ototal
+            assert np.array_equal(bits[:nb], obits) and np.array_equal(index, oindex)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [0, 1, 4097, 100003, 1 << 20])
 def test_build_table(mode, n):
