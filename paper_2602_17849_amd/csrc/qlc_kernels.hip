@@ -1279,7 +1279,8 @@ union BatchEncSmem {
   EncSmem enc;
 };
 
-__global__ __launch_bounds__(kEncThreads) void k_encode_batched(
+// At most 128 VGPRs, so that four workgroups share a CU (LDS allows it).
+__global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
     const qlc_job* __restrict__ jobs, uint32_t mode, uint32_t log2_seg, uint32_t log2_chunk,
     BatchHeader* __restrict__ hdr, BatchJobState* __restrict__ js,
     uint64_t* __restrict__ job_hist, const uint32_t* __restrict__ seg_job,
