@@ -644,7 +644,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   const uint64_t my_bits =
       seg_bits ? seg_bits[seg]
                : block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
-  const bool bad_table = S.bad_table != 0;
   if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
   uint64_t pre = 0;
   for (uint32_t k = tid; k < seg; k += kEncThreads) {
@@ -655,6 +654,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     pre += w & kValueMask;
   }
   const uint64_t G = block_sum_u64(pre, S.red);
+  // read after the block sum's barriers, so every thread's length check is in
+  const bool bad_table = S.bad_table != 0;
   if (seg == nseg - 1 && tid == 0) *total_out = G + my_bits;
 
   const uint64_t seg0 = (uint64_t)seg << log2_seg;

@@ -160,6 +160,28 @@ def test_capacity_error():
     assert not bits[cap:].any()          # nothing written past the capacity
 
 
+@pytest.mark.parametrize("sym,length", [(0, 0), (131, 12), (255, 2)])
+def test_bad_table_rejected(sym, length):
+    """A given table with a code length outside 3..11 is rejected by every
+    workgroup of the encode (device error word), plain and batched."""
+    n = 5_000_000
+    x = datagen.gaussian(n, 13).numpy()
+    t = table_from_oracle(oracle.build_table(oracle.histogram(x), 0))
+    enc = t[:512].view(torch.int16)
+    enc[sym] = (enc[sym] & 0x7FF) | (length << 11)
+    err, bits, nbytes, index, total = gpu_encode(to_dev(x), t, 4096)
+    assert err == qlc.QLC_ERR_INVALID_ARGUMENT
+    b = qlc.Batch([n, 1000], chunk_symbols=4096, device=DEV, capacity="bound", build_table=False)
+    b.input(0).copy_(to_dev(x))
+    b.input(1).copy_(to_dev(x[:1000]))
+    b.table(0).copy_(t)
+    b.table(1).copy_(table_from_oracle(oracle.build_table(oracle.histogram(x[:1000]), 0)))
+    ws = b.workspace()
+    b.encode(ws)
+    torch.cuda.synchronize()
+    assert int(b.err[0]) == qlc.QLC_ERR_INVALID_ARGUMENT and int(b.err[1]) == 0
+
+
 def test_deterministic_repeat():
     x = to_dev(datagen.gaussian(1 << 20, 9).numpy())
     t = gpu_table(x, 0)
