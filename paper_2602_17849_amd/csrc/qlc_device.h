@@ -11,43 +11,64 @@ namespace qlc {
 // Candidate width tuples of the layout search (compile-time table).
 // Non-decreasing 8-tuples over 0..8 whose greedy fill leaves every area
 // non-empty (the first seven areas hold fewer than 256 ranks) and covers all
-// 256 ranks, in lexicographic order; widths packed as 4-bit nibbles.
+// 256 ranks.  Entries with at most four distinct widths come first (the
+// quad search reads only those), each part in lexicographic order; `lex` is
+// the tuple's position in the full lexicographic order (the tie-break).
+// Widths are packed as 4-bit nibbles; `ends` holds the greedy fill's end
+// rank of areas 0..6, one byte each (area 7 ends at 256).
 // ---------------------------------------------------------------------------
 constexpr int kNumCandidates = 3639;
+constexpr int kNumQuadCandidates = 1308;
+
+struct Candidate {
+  uint32_t packed;
+  uint32_t lex;
+  uint64_t ends;
+};
 
 struct CandidateTable {
-  uint32_t packed[kNumCandidates];
-  uint8_t distinct[kNumCandidates];
-  int count;
+  Candidate c[kNumCandidates];
+  int count, quad;
 };
 
 constexpr CandidateTable make_candidate_table() {
   CandidateTable t{};
   int w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int n = 0;
-  while (true) {
-    uint32_t head = 0;
-    for (int a = 0; a < 7; ++a) head += 1u << w[a];
-    if (head < 256 && head + (1u << w[7]) >= 256) {
-      uint32_t pk = 0;
-      int d = 1;
-      for (int a = 0; a < 8; ++a) {
-        pk |= uint32_t(w[a]) << (4 * a);
-        if (a > 0 && w[a] != w[a - 1]) ++d;
+  int n = 0, nq = 0;
+  // two passes over the lexicographic order: quad tuples, then the others
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int a = 0; a < 8; ++a) w[a] = 0;
+    int lex = 0;
+    while (true) {
+      uint32_t head = 0;
+      for (int a = 0; a < 7; ++a) head += 1u << w[a];
+      if (head < 256 && head + (1u << w[7]) >= 256) {
+        uint32_t pk = 0;
+        uint64_t ends = 0;
+        uint32_t f = 0;
+        int d = 1;
+        for (int a = 0; a < 8; ++a) {
+          pk |= uint32_t(w[a]) << (4 * a);
+          if (a > 0 && w[a] != w[a - 1]) ++d;
+          f += 1u << w[a];
+          if (a < 7) ends |= uint64_t(f) << (8 * a);
+        }
+        if ((d <= 4) == (pass == 0)) {
+          if (n < kNumCandidates) t.c[n] = Candidate{pk, uint32_t(lex), ends};
+          ++n;
+          if (pass == 0) ++nq;
+        }
+        ++lex;
       }
-      if (n < kNumCandidates) {
-        t.packed[n] = pk;
-        t.distinct[n] = uint8_t(d);
-      }
-      ++n;
+      int pos = 7;
+      while (pos >= 0 && w[pos] == 8) --pos;
+      if (pos < 0) break;
+      ++w[pos];
+      for (int a = pos + 1; a < 8; ++a) w[a] = w[pos];
     }
-    int pos = 7;
-    while (pos >= 0 && w[pos] == 8) --pos;
-    if (pos < 0) break;
-    ++w[pos];
-    for (int a = pos + 1; a < 8; ++a) w[a] = w[pos];
   }
   t.count = n;
+  t.quad = nq;
   return t;
 }
 

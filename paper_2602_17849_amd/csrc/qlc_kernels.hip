@@ -11,6 +11,8 @@ namespace qlc {
 
 __constant__ CandidateTable g_candidates = make_candidate_table();
 static_assert(make_candidate_table().count == kNumCandidates, "candidate count");
+static_assert(make_candidate_table().quad == kNumQuadCandidates, "quad candidate count");
+
 
 // ===========================================================================
 // Table construction (Implementation section, Tables 1-4).  Run by one
@@ -20,6 +22,7 @@ struct TableSmem {
   uint64_t h[256];
   uint64_t P[257];          // P[r] = sum of the counts of ranks < r
   uint64_t wave_min[16];
+  uint32_t best_packed;
   uint32_t rank[256];       // symbol -> rank
   uint32_t r2s[256];        // rank -> symbol
   uint32_t width[8], first[8], count[8], offset[8];
@@ -39,16 +42,27 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   __syncthreads();
 
   // Rank = number of symbols that sort before s: larger count, or equal
-  // count and smaller symbol value.
-  for (int s = tid; s < 256; s += nt) {
-    const uint64_t hs = S.h[s];
-    uint32_t r = 0;
-    for (int u = 0; u < 256; ++u) {
-      const uint64_t hu = S.h[u];
-      r += (hu > hs) | ((hu == hs) & (u < s));
+  // count and smaller symbol value.  Every wave holds all 256 counts (four
+  // per lane) and ranks its share of the symbols with ballots: one compare
+  // per held count and a population count per symbol.
+  {
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    uint64_t hu[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hu[k] = S.h[lane + 64 * k];
+    for (int s = wave; s < 256; s += nw) {
+      const uint64_t hs = S.h[s];
+      uint32_t r = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int u = lane + 64 * k;
+        r += (uint32_t)__popcll(__ballot((hu[k] > hs) || (hu[k] == hs && u < s)));
+      }
+      if (lane == 0) {
+        S.rank[s] = r;
+        S.r2s[r] = s;
+      }
     }
-    S.rank[s] = r;
-    S.r2s[r] = s;
   }
   __syncthreads();
 
@@ -77,26 +91,32 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   } else if (mode == QLC_LAYOUT_PAPER_T2) {
     packed = kPaperT2Packed;
   } else {
-    const uint32_t max_distinct = (mode == QLC_LAYOUT_SEARCH_QUAD) ? 4u : 8u;
+    // cost = 3 * N + sum_a width_a * (ranks' counts in area a); the area
+    // ends come with the candidate, so the eight prefix-sum reads are
+    // independent.
+    const int ncand = (mode == QLC_LAYOUT_SEARCH_QUAD) ? kNumQuadCandidates : kNumCandidates;
+    const uint64_t pN = S.P[256];
     uint64_t best = ~0ull;
-    for (int c = tid; c < kNumCandidates; c += nt) {
-      if (g_candidates.distinct[c] > max_distinct) continue;
-      const uint32_t pk = g_candidates.packed[c];
-      uint32_t f = 0;
-      uint64_t cost = 0;
+    uint32_t best_pk = 0;
+    for (int i = tid; i < ncand; i += nt) {
+      const Candidate cd = g_candidates.c[i];
+      uint64_t cost = 3 * pN;
+      uint64_t prev = 0;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const uint32_t b = (pk >> (4 * a)) & 15u;
-        const uint32_t cap = 1u << b;
-        const uint32_t cnt = cap < 256u - f ? cap : 256u - f;
-        cost += (uint64_t)(3 + b) * (S.P[f + cnt] - S.P[f]);
-        f += cnt;
+        const uint32_t e = a < 7 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
+        const uint64_t pe = S.P[e];
+        cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
+        prev = pe;
       }
-      const uint64_t key = (cost << 12) | (uint64_t)c;
-      best = key < best ? key : best;
+      const uint64_t key = (cost << 12) | (uint64_t)cd.lex;
+      if (key < best) {
+        best = key;
+        best_pk = cd.packed;
+      }
     }
-    best = wave_min_u64(best);
-    if ((tid & 63) == 0) S.wave_min[tid >> 6] = best;
+    const uint64_t wmin = wave_min_u64(best);
+    if ((tid & 63) == 0) S.wave_min[tid >> 6] = wmin;
     __syncthreads();
     if (tid == 0) {
       uint64_t m = S.wave_min[0];
@@ -104,7 +124,10 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
       S.wave_min[0] = m;
     }
     __syncthreads();
-    packed = g_candidates.packed[S.wave_min[0] & 0xFFF];
+    // keys are unique (lex differs), so exactly one thread holds the minimum
+    if (best == S.wave_min[0]) S.best_packed = best_pk;
+    __syncthreads();
+    packed = S.best_packed;
   }
 
   // Greedy fill, offsets (an 8-bit area carries the raw rank), cost.
