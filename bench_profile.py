@@ -1,17 +1,18 @@
 """rocprofv3 measurements behind bench.py's roofline line.
 
-    python3 bench_profile.py collect [--chunk C]
+    python3 bench_profile.py collect [--chunk C] [--out DIR]
 
-runs, on the GPU machine, from the repository root:
+runs, on a machine with the GPU, from the repository root:
   1. rocprofv3 --kernel-trace --stats on bench.py (per-kernel durations);
   2. rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE, on bench.py;
   3. the same two counters on a plain 256 MiB device copy (torch copy_),
      whose true bytes are known, to scale the counters to bytes;
-and writes gpurun_out/bench_profile/traffic.json (HBM bytes per launch of
-each libqlc kernel, tagged with the hash of the kernel sources) and
-gpurun_out/bench_profile/kernels_single_tensor_256MiB.md (the summary, with
-the commands); both are then copied into profiles/, where bench.py reads
-traffic.json while the kernel sources still match its hash.
+and writes DIR/traffic.json (HBM bytes per launch of each libqlc kernel,
+tagged with the hash of the kernel sources) and
+DIR/kernels_single_tensor_256MiB.md (the summary, with the commands, paths
+relative to the repository root); both are then copied into profiles/,
+where bench.py reads traffic.json while the kernel sources still match its
+hash.  DIR defaults to profile_runs/ (raw rocprofv3 output, not committed).
 
     python3 bench_profile.py copy     # the calibration workload itself
 """
@@ -26,7 +27,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-OUT = os.path.join(ROOT, "gpurun_out", "bench_profile")
+OUT = "profile_runs"  # relative to ROOT; --out overrides
 COPY_BYTES = 256 << 20
 
 
@@ -161,6 +162,8 @@ if __name__ == "__main__":
         chunk = 2048
         if "--chunk" in sys.argv:
             chunk = int(sys.argv[sys.argv.index("--chunk") + 1])
+        if "--out" in sys.argv:
+            OUT = sys.argv[sys.argv.index("--out") + 1]
         os.chdir("/tmp")
         os.environ["TMPDIR"] = "/tmp"
         os.chdir(ROOT)
