@@ -93,7 +93,7 @@ BATCH_WORKLOAD = ("1152 shards (18 x 64), sizes log-uniform in 1-32 MiB, multipl
                   "weights by i mod 3, block-32 e4m3; per-shard SEARCH_QUAD table")
 
 
-def run_batched(dev, steps, plain_steps=2):
+def run_batched(dev, steps, plain_steps=2, fixed=None):
     """Batched form vs plain per-shard launches on the 1152-shard workload."""
     import torch
 
@@ -110,7 +110,10 @@ def run_batched(dev, steps, plain_steps=2):
     print("batched: %d shards, %.2f GiB generated" % (S, total / 2**30), file=sys.stderr,
           flush=True)
 
-    ch = autotune.tune_batched(A, mode)
+    if fixed:  # (C, log2_segment, lag): the autotuner is skipped (profiling runs)
+        ch = autotune.Choice(fixed[0], fixed[1], fixed[2], 0.0, 0.0)
+    else:
+        ch = autotune.tune_batched(A, mode)
     C = ch.chunk_symbols
     A.set_chunk(C)
     A.index.zero_()  # drop the entries other chunk sizes left while tuning
@@ -286,6 +289,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--batched-tuning", default="",
+                    help="C,LOG2_SEGMENT,LAG for the batched form instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -398,7 +403,8 @@ def main():
     if not args.no_batched:
         del x, out, bits, ws
         torch.cuda.empty_cache()
-        res["batched"] = run_batched(dev, max(3, min(args.steps, 10)))
+        fixed = tuple(int(v) for v in args.batched_tuning.split(",")) if args.batched_tuning else None
+        res["batched"] = run_batched(dev, max(3, min(args.steps, 10)), fixed=fixed)
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = run_serving(dev, args.serve_seconds)

@@ -15,6 +15,8 @@ where bench.py reads traffic.json while the kernel sources still match its
 hash.  DIR defaults to profile_runs/ (raw rocprofv3 output, not committed).
 
     python3 bench_profile.py copy     # the calibration workload itself
+    python3 bench_profile.py batched [--tuning C,LOG2_SEGMENT,LAG] [--out DIR]
+        # kernel durations of the batched form on the 1152-shard workload
 """
 from __future__ import annotations
 
@@ -155,9 +157,46 @@ def collect(chunk):
     print("\n".join(lines))
 
 
+def collect_batched(tuning):
+    """Kernel durations of the batched form on the 1152-shard workload, at a
+    fixed tuning (no autotuner calls in the trace)."""
+    os.makedirs(OUT, exist_ok=True)
+    cmd = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv",
+           "-d", os.path.join(OUT, "trace_batched"), "-o", "trace", "--",
+           "python3", "bench.py", "--steps", "3", "--warmup", "1", "--no-cpu-baseline",
+           "--no-serving", "--batched-tuning", tuning]
+    run(cmd, os.path.join(OUT, "trace_batched.log"))
+    stats = kernel_stats(os.path.join(OUT, "trace_batched"))
+    c, l2, lag = tuning.split(",")
+    lines = ["# libqlc batched kernels on 1152 shards (1-32 MiB, 10.25 GiB)", "",
+             "Chunk %s symbols, segments of 2^%s symbols, lag %s.  Kernel durations: `%s` "
+             "(run from the repository root).  Each call of k_encode_batched / "
+             "k_decode_batched processes all 1152 shards; the single-tensor kernels "
+             "of the same run (the 256 MiB tensor and the plain per-shard comparison) "
+             "are listed for reference." % (c, l2, lag, " ".join(cmd)), "",
+             "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: short(r.get("Name", ""))):
+        nm = short(r.get("Name", ""))
+        if not nm.startswith("k_"):
+            continue
+        lines.append("| %s | %s | %.2f | %.2f | %.2f |" % (
+            nm, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3))
+    with open(os.path.join(OUT, "kernels_batched_1152_shards.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "copy":
         copy_workload()
+    elif len(sys.argv) > 1 and sys.argv[1] == "batched":
+        if "--out" in sys.argv:
+            OUT = sys.argv[sys.argv.index("--out") + 1]
+        os.environ["TMPDIR"] = "/tmp"
+        os.chdir(ROOT)
+        collect_batched(sys.argv[sys.argv.index("--tuning") + 1] if "--tuning" in sys.argv
+                        else "2048,19,0")
     else:
         chunk = 2048
         if "--chunk" in sys.argv:
