@@ -1,0 +1,85 @@
+"""Parity at the benchmark's full size and launch configuration: the 256 MiB
+Laplace e4m3 tensor (8192 x 32768, seed 1), per-tensor SEARCH_QUAD table,
+chunks of 2048 symbols, compressed by qlc_compress and decoded by qlc_decode
+exactly as bench.py times them.  The oracle is too slow for the whole
+stream, so it checks what it can at this size: the table (from the oracle's
+own histogram of all 268 M bytes), total bits against the closed form
+sum h * len, every index step against the chunk's summed code lengths, the
+stream bits of sampled chunks (first, last and 62 random ones) against the
+oracle's encoding of those chunks, and the full round trip."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DEV, assert_table_equal
+from paper_2602_17849_amd import datagen, qlc
+
+pytestmark = pytest.mark.gpu
+
+C = 2048
+
+
+def _bits(stream: np.ndarray, start: int, count: int) -> np.ndarray:
+    """Bits [start, start + count) of an MSB-first byte stream."""
+    b0, b1 = start // 8, (start + count + 7) // 8
+    u = np.unpackbits(stream[b0:b1])
+    return u[start - 8 * b0:start - 8 * b0 + count]
+
+
+@pytest.fixture(scope="module")
+def compressed():
+    x = datagen.single_tensor_laplace(device=DEV)
+    n = x.numel()
+    obj = qlc.compress(x, mode=qlc.LAYOUT_SEARCH_QUAD, chunk_symbols=C)
+    torch.cuda.synchronize()
+    assert int(obj.err.item()) == 0
+    return x, obj
+
+
+def test_fullsize_table_and_totals(compressed):
+    x, obj = compressed
+    xh = x.cpu().numpy()
+    h = oracle.histogram(xh)
+    ot = oracle.build_table(h, qlc.LAYOUT_SEARCH_QUAD)
+    assert_table_equal(obj.table, ot)
+    total = obj.total_bits()
+    assert total == int((h.astype(np.uint64) * ot.len.astype(np.uint64)).sum())
+    # every index step is the sum of the chunk's code lengths
+    k = qlc.qlc_chunk_count(x.numel(), C)
+    index = obj.index[:k].cpu().numpy().astype(np.int64)
+    lens = ot.len.astype(np.uint8)[xh]
+    per_chunk = lens.reshape(-1, C).sum(axis=1, dtype=np.int64)
+    assert index[0] == 0
+    assert np.array_equal(np.diff(index), per_chunk[:-1])
+    assert index[-1] + per_chunk[-1] == total
+
+
+def test_fullsize_sampled_chunks_match_oracle(compressed):
+    x, obj = compressed
+    xh = x.cpu().numpy()
+    ot = oracle.build_table(oracle.histogram(xh), qlc.LAYOUT_SEARCH_QUAD)
+    k = qlc.qlc_chunk_count(x.numel(), C)
+    index = obj.index[:k].cpu().numpy().astype(np.int64)
+    total = obj.total_bits()
+    stream = obj.bits[:obj.nbytes()].cpu().numpy()
+    rng = np.random.default_rng(17)
+    chunks = [0, k - 1] + sorted(rng.choice(np.arange(1, k - 1), 62, replace=False).tolist())
+    for j in chunks:
+        sym = xh[j * C:(j + 1) * C]
+        st, obits, oindex, ototal = oracle.encode(sym, ot, C)
+        assert st == 0
+        end = index[j + 1] if j + 1 < k else total
+        assert end - index[j] == ototal, j
+        assert np.array_equal(_bits(stream, int(index[j]), ototal), _bits(obits, 0, ototal)), j
+    # the stream's padding after the last code is zero
+    tail = _bits(stream, total, 8 * obj.nbytes() - total)
+    assert not tail.any()
+
+
+def test_fullsize_round_trip(compressed):
+    x, obj = compressed
+    out, err = qlc.decompress(obj)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0
+    assert torch.equal(out, x)
