@@ -1,4 +1,4 @@
-"""Parity at the benchmark's full size and launch configuration: the 256 MiB
+"""Parity at the benchmarks' full sizes and launch configurations: the 256 MiB
 Laplace e4m3 tensor (8192 x 32768, seed 1), per-tensor SEARCH_QUAD table,
 chunks of 2048 symbols, compressed by qlc_compress and decoded by qlc_decode
 exactly as bench.py times them.  The oracle is too slow for the whole
@@ -6,7 +6,9 @@ stream, so it checks what it can at this size: the table (from the oracle's
 own histogram of all 268 M bytes), total bits against the closed form
 sum h * len, every index step against the chunk's summed code lengths, the
 stream bits of sampled chunks (first, last and 62 random ones) against the
-oracle's encoding of those chunks, and the full round trip."""
+oracle's encoding of those chunks, and the full round trip.  Also the
+batched form on the whole 1152-shard workload, with sampled shards against
+the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -83,3 +85,37 @@ def test_fullsize_round_trip(compressed):
     torch.cuda.synchronize()
     assert int(err.item()) == 0
     assert torch.equal(out, x)
+
+
+def test_fullsize_batched_1152_shards():
+    """The batched form on the full 1152-shard workload (10.25 GiB) at the
+    benchmark's tuned setting: no job errors, every shard round-trips, and
+    ten sampled shards (smallest, largest, eight random) have the oracle's
+    table, total, bitstream and chunk index."""
+    sizes = datagen.shard_sizes()
+    b = qlc.Batch(sizes, chunk_symbols=C, device=DEV)
+    for i, n in enumerate(sizes):
+        b.input(i).copy_(datagen.shard(i, n, device=DEV))
+    tuning = (19, 0, 0, 0)
+    ws = b.workspace(tuning)
+    b.encode(ws, qlc.LAYOUT_SEARCH_QUAD, tuning)
+    b.decode(ws, tuning)
+    torch.cuda.synchronize()
+    assert not b.err.any().item()
+    assert torch.equal(b.out, b.inp)
+    rng = np.random.default_rng(23)
+    picks = {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    picks |= set(rng.choice(len(sizes), 8, replace=False).tolist())
+    for i in sorted(picks):
+        xh = b.input(i).cpu().numpy()
+        ot = oracle.build_table(oracle.histogram(xh), qlc.LAYOUT_SEARCH_QUAD)
+        assert_table_equal(b.table(i), ot)
+        st, obits, oindex, ototal = oracle.encode(xh, ot, C)
+        total = int(b.total[i].item())
+        assert st == 0 and total == ototal, i
+        nb = 4 * ((total + 31) // 32)
+        assert np.array_equal(b.bitstream(i, nb).cpu().numpy(), obits), i
+        assert np.array_equal(b.chunk_index(i).cpu().numpy().astype(np.uint64),
+                              oindex.astype(np.uint64)), i
+    del b, ws
+    torch.cuda.empty_cache()
