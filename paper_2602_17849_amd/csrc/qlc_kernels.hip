@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
 // ===========================================================================
 struct EncSmem {
   uint32_t lut[256];        // code | length << 16 (halves feed SDWA operands)
-  __attribute__((aligned(16))) uint32_t words[kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
+  __attribute__((aligned(16))) uint32_t words[2][kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
   uint64_t red[kEncThreads / 64];
   uint32_t wave_sum[kEncThreads / 64];
   uint32_t seg, epoch, cap_hit, bad_table;
@@ -408,6 +408,7 @@ struct EncSeg {
   __amdgpu_buffer_rsrc_t out_rsrc;   // stream words from seg_w0 on, clipped at cap_words
   uint64_t* index_out;
   uint4 nx0, nx1;                    // the next full tile's input (prefetched)
+  uint32_t buf;                      // word buffer of the current tile
 };
 
 // One tile of 8192 symbols at t0 (kFull: a whole tile; else the input's
@@ -421,6 +422,7 @@ template <bool kFull>
 __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, uint32_t tid) {
   const uint32_t lane = tid & 63, wave = tid >> 6;
   bool cap = false;
+  uint32_t* const Wd = S.words[E.buf];
   uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (whole tiles)
   uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
   if (kFull) {
@@ -472,9 +474,9 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
     Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
     if (kFull) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) P0.put(S.words, pc[k], pl[k]);
+      for (int k = 0; k < 8; ++k) P0.put(Wd, pc[k], pl[k]);
 #pragma unroll
-      for (int k = 8; k < 16; ++k) P1.put(S.words, pc[k], pl[k]);
+      for (int k = 8; k < 16; ++k) P1.put(Wd, pc[k], pl[k]);
     } else {
 #pragma unroll 1
       for (int k = 0; k < 32; ++k) {
@@ -482,13 +484,13 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
             t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
         if (i < E.seg1) {
           const uint32_t e = S.lut[E.in[i]];
-          if (k < 16) P0.put(S.words, e & 0xFFFFu, e >> 16);
-          else P1.put(S.words, e & 0xFFFFu, e >> 16);
+          if (k < 16) P0.put(Wd, e & 0xFFFFu, e >> 16);
+          else P1.put(Wd, e & 0xFFFFu, e >> 16);
         }
       }
     }
-    P0.finish(S.words);
-    P1.finish(S.words);
+    P0.finish(Wd);
+    P1.finish(Wd);
     // chunk index entries: a run's first symbol may start a chunk
     const uint64_t i0s = t0 + (uint64_t)tid * 16;
     const uint64_t i1s = i0s + kEncTile / 2;
@@ -506,7 +508,7 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
   // four words per thread per store; the buffer resource drops anything
   // past the capacity
   for (uint32_t i = 4 * tid; i < nw; i += 4 * kEncThreads) {
-    uint4* src = reinterpret_cast<uint4*>(&S.words[i]);
+    uint4* src = reinterpret_cast<uint4*>(&Wd[i]);
     if (i + 4 <= nw) {
       const uint4 v = *src;
       *src = make_uint4(0, 0, 0, 0);
@@ -515,26 +517,30 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
       __builtin_amdgcn_raw_buffer_store_b128(ov, E.out_rsrc, (wr + i) * 4, 0, 0);
     } else {
       for (uint32_t k = i; k < nw; ++k) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bswap32(S.words[k]), E.out_rsrc,
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bswap32(Wd[k]), E.out_rsrc,
                                               (wr + k) * 4, 0, 0);
-        S.words[k] = 0;
+        Wd[k] = 0;
       }
     }
   }
-  __syncthreads();
   if (tid == 0 && !final_tile) {
-    // the partial last word becomes word 0 of the next tile
-    const uint32_t carry = S.words[endb >> 5];
-    S.words[endb >> 5] = 0;
-    S.words[0] = carry;
+    // the partial last word (no store above touches it) becomes word 0 of
+    // the other buffer, which the next tile packs into; this buffer is not
+    // packed again before every thread has passed the next tile's barriers
+    const uint32_t carry = Wd[endb >> 5];
+    Wd[endb >> 5] = 0;
+    S.words[E.buf ^ 1][0] = carry;
   }
+  E.buf ^= 1;
   E.R += tile_bits;
   return cap;
 }
 
 // Encode symbols [seg0, seg1) of `in`, whose first code starts at stream
 // bit G (kEncThreads threads, tid = threadIdx.x).  On entry S.lut holds the encoder LUT and
-// S.words[1..] are zero; on return S.words[1..] are zero again.  Every
+// both word buffers are zero except word 0 of buffer 0 (written here).  Tiles
+// alternate between the two buffers, so a tile's stores and the next
+// tile's packing need no barrier between them.  Every
 // whole stream word of the segment is stored; its partial first word also
 // carries the previous segment's last bits (recomputed from the 16 symbols
 // before seg0); its partial last word is left to the next segment, unless
@@ -557,7 +563,7 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
       }
       w0 = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
     }
-    S.words[0] = w0;
+    S.words[0][0] = w0;
   }
   EncSeg E;
   E.in = in;
@@ -576,6 +582,7 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
   E.out_rsrc = __builtin_amdgcn_make_buffer_rsrc(
       bits_out + (cap_words > E.seg_w0 ? E.seg_w0 : 0), (short)0,
       (int)(uint32_t)(room < 0xFFFFFFF0ull ? room : 0xFFFFFFF0ull), 0x00020000);
+  E.buf = 0;
   E.nx0 = make_uint4(0, 0, 0, 0);
   E.nx1 = E.nx0;
   if (seg0 + kEncTile <= seg1) {
@@ -654,7 +661,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   }
   const uint32_t e_t = table->enc[tid];
   S.lut[tid] = enc_entry(e_t);
-  for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) S.words[w] = 0;
+  for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) (&S.words[0][0])[w] = 0;
   __syncthreads();
   // A table whose code lengths leave 3..11 is rejected (keeps every LDS
   // index of the packer in bounds without per-symbol clamps).
@@ -1359,7 +1366,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
         S.enc.bad_table = 0;
         S.enc.cap_hit = 0;
       }
-      for (uint32_t w = tid; w < sizeof(S.enc.words) / 4; w += kEncThreads) S.enc.words[w] = 0;
+      for (uint32_t w = tid; w < sizeof(S.enc.words) / 4; w += kEncThreads) (&S.enc.words[0][0])[w] = 0;
       __syncthreads();
       if (tid < 128) {
         const uint32_t* tw = reinterpret_cast<const uint32_t*>(jb.table);
