@@ -85,8 +85,20 @@ typedef enum qlc_layout_mode {
   QLC_LAYOUT_SEARCH_QUAD = 0, /* cheapest tuple with <= 4 distinct lengths   */
   QLC_LAYOUT_SEARCH_ANY = 1,  /* cheapest tuple, any number of lengths       */
   QLC_LAYOUT_PAPER_T1 = 2,    /* Table 1: widths 3,3,3,3,3,4,5,8             */
-  QLC_LAYOUT_PAPER_T2 = 3     /* Table 2: widths 1,3,3,3,3,5,5,8             */
+  QLC_LAYOUT_PAPER_T2 = 3,    /* Table 2: widths 1,3,3,3,3,5,5,8             */
+  /* Cheapest tuple with at most k distinct code lengths, k = 1..8 (the
+   * number of distinct lengths is one of the knobs the Conclusion section
+   * leaves open; k = 4 gives SEARCH_QUAD's table, k = 8 SEARCH_ANY's). */
+  QLC_LAYOUT_SEARCH_DISTINCT_1 = 17,
+  QLC_LAYOUT_SEARCH_DISTINCT_2 = 18,
+  QLC_LAYOUT_SEARCH_DISTINCT_3 = 19,
+  QLC_LAYOUT_SEARCH_DISTINCT_4 = 20,
+  QLC_LAYOUT_SEARCH_DISTINCT_5 = 21,
+  QLC_LAYOUT_SEARCH_DISTINCT_6 = 22,
+  QLC_LAYOUT_SEARCH_DISTINCT_7 = 23,
+  QLC_LAYOUT_SEARCH_DISTINCT_8 = 24
 } qlc_layout_mode;
+#define QLC_LAYOUT_SEARCH_DISTINCT(k) ((qlc_layout_mode)(16 + (k)))
 
 /* A complete QLC table (Tables 1-4 in one record).  Plain old data, 1088
  * bytes, device resident when passed to the codec entry points. */

@@ -174,14 +174,14 @@ qlc_status qlc_histogram_accumulate(const uint8_t* in, uint64_t n, uint64_t* his
 
 qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
                                     qlc_table* table_out, hipStream_t stream) {
-  if (!hist || !table_out || (uint32_t)mode > QLC_LAYOUT_PAPER_T2) return QLC_ERR_INVALID_ARGUMENT;
+  if (!hist || !table_out || !valid_layout_mode((uint32_t)mode)) return QLC_ERR_INVALID_ARGUMENT;
   if (!aligned(hist, 8) || !aligned(table_out, 16)) return QLC_ERR_INVALID_ARGUMENT;
   return hip_status(launch_table_from_hist(hist, (uint32_t)mode, table_out, stream));
 }
 
 qlc_status qlc_build_table(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
                            qlc_table* table_out, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if ((n && !in) || !table_out || !ws || (uint32_t)mode > QLC_LAYOUT_PAPER_T2 ||
+  if ((n && !in) || !table_out || !ws || !valid_layout_mode((uint32_t)mode) ||
       n >= QLC_MAX_SYMBOLS_PER_CALL)
     return QLC_ERR_INVALID_ARGUMENT;
   if (!aligned(in, 16) || !aligned(table_out, 16) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
@@ -234,7 +234,7 @@ qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode, qlc
                         uint64_t* chunk_index_out, uint64_t* total_bits_out, uint32_t* err_out,
                         void* ws, size_t ws_bytes, hipStream_t stream) {
   uint32_t log2c = 0;
-  if ((uint32_t)mode > QLC_LAYOUT_PAPER_T2) return QLC_ERR_INVALID_ARGUMENT;
+  if (!valid_layout_mode((uint32_t)mode)) return QLC_ERR_INVALID_ARGUMENT;
   qlc_status st = check_encode_args(in, n, table_out, chunk_symbols, bits_out, bits_capacity_bytes,
                                     chunk_index_out, total_bits_out, err_out, ws, ws_bytes, &log2c);
   if (st != QLC_OK) return st;
@@ -281,7 +281,7 @@ qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_m
                               uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning, void* ws,
                               size_t ws_bytes, hipStream_t stream) {
   uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
-  if (!valid_chunk(chunk_symbols, &log2c) || (uint32_t)mode > QLC_LAYOUT_PAPER_T2 ||
+  if (!valid_chunk(chunk_symbols, &log2c) || !valid_layout_mode((uint32_t)mode) ||
       !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return QLC_ERR_INVALID_ARGUMENT;
   if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;

@@ -13,7 +13,8 @@ namespace qlc {
 // non-empty (the first seven areas hold fewer than 256 ranks) and covers all
 // 256 ranks.  Entries with at most four distinct widths come first (the
 // quad search reads only those), each part in lexicographic order; `lex` is
-// the tuple's position in the full lexicographic order (the tie-break).
+// the tuple's position in the full lexicographic order (the tie-break) in
+// its low 16 bits and the number of distinct widths above them.
 // Widths are packed as 4-bit nibbles; `ends` holds the greedy fill's end
 // rank of areas 0..6, one byte each (area 7 ends at 256).
 // ---------------------------------------------------------------------------
@@ -54,7 +55,7 @@ constexpr CandidateTable make_candidate_table() {
           if (a < 7) ends |= uint64_t(f) << (8 * a);
         }
         if ((d <= 4) == (pass == 0)) {
-          if (n < kNumCandidates) t.c[n] = Candidate{pk, uint32_t(lex), ends};
+          if (n < kNumCandidates) t.c[n] = Candidate{pk, uint32_t(lex) | (uint32_t(d) << 16), ends};
           ++n;
           if (pass == 0) ++nq;
         }

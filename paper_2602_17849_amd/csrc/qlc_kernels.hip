@@ -94,12 +94,16 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     // cost = 3 * N + sum_a width_a * (ranks' counts in area a); the area
     // ends come with the candidate, so the eight prefix-sum reads are
     // independent.
-    const int ncand = (mode == QLC_LAYOUT_SEARCH_QUAD) ? kNumQuadCandidates : kNumCandidates;
+    const uint32_t max_distinct = mode == QLC_LAYOUT_SEARCH_QUAD ? 4u
+                                  : mode == QLC_LAYOUT_SEARCH_ANY ? 8u
+                                                                  : mode - 16u;
+    const int ncand = max_distinct <= 4u ? kNumQuadCandidates : kNumCandidates;
     const uint64_t pN = S.P[256];
     uint64_t best = ~0ull;
     uint32_t best_pk = 0;
     for (int i = tid; i < ncand; i += nt) {
       const Candidate cd = g_candidates.c[i];
+      if ((cd.lex >> 16) > max_distinct) continue;
       uint64_t cost = 3 * pN;
       uint64_t prev = 0;
 #pragma unroll
@@ -109,7 +113,7 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
         cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
         prev = pe;
       }
-      const uint64_t key = (cost << 12) | (uint64_t)cd.lex;
+      const uint64_t key = (cost << 12) | (uint64_t)(cd.lex & 0xFFFFu);
       if (key < best) {
         best = key;
         best_pk = cd.packed;

@@ -30,6 +30,13 @@ LAYOUT_SEARCH_ANY = 1
 LAYOUT_PAPER_T1 = 2
 LAYOUT_PAPER_T2 = 3
 
+
+def LAYOUT_SEARCH_DISTINCT(k: int) -> int:
+    """Layout mode: cheapest tuple with at most k (1..8) distinct code lengths."""
+    if not 1 <= k <= 8:
+        raise ValueError("k must be in 1..8")
+    return 16 + k
+
 TABLE_BYTES = 1088
 SERIALIZED_TABLE_BYTES = 264
 MIN_CHUNK = 256

@@ -55,6 +55,11 @@ def test_argument_errors_are_synchronous():
     assert L.qlc_encode(ws + 1, 10, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_encode(ws, 10, ws, 4096, ws, 64, ws, ws, ws, ws, 16, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_build_table(ws, 10, 9, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    for bad_mode in (4, 16, 25, 255):
+        assert L.qlc_build_table(ws, 10, bad_mode, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+        assert L.qlc_table_from_histogram(ws, bad_mode, ws, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    with pytest.raises(ValueError):
+        qlc.LAYOUT_SEARCH_DISTINCT(0)
     assert L.qlc_histogram(0, 10, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_histogram_accumulate(0, 10, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_histogram_accumulate(ws, 10, ws + 4, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT

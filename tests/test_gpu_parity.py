@@ -71,6 +71,37 @@ def test_build_table(mode, n):
         assert_table_equal(t, oracle.build_table(oracle.histogram(x), mode))
 
 
+@pytest.mark.parametrize("k", range(1, 9))
+def test_distinct_cap_modes(k):
+    """SEARCH_DISTINCT_k (at most k distinct code lengths): the GPU table
+    equals the oracle's capped search on skewed, uniform, tied and
+    single-symbol histograms; a compress with it matches the oracle's
+    encode and round-trips."""
+    mode = qlc.LAYOUT_SEARCH_DISTINCT(k)
+    rng = np.random.default_rng(40 + k)
+    hists = [(rng.pareto(1.0, 256) * 1000).astype(np.uint64), np.ones(256, np.uint64),
+             np.repeat(np.arange(8, dtype=np.uint64), 32) * 5]
+    one = np.zeros(256, np.uint64)
+    one[17] = 1000
+    hists.append(one)
+    for hh in hists:
+        t = qlc.new_table()
+        qlc.qlc_table_from_histogram(to_dev(hh.astype(np.int64)), mode, t)
+        torch.cuda.synchronize()
+        assert_table_equal(t, oracle.build_table_general(hh, 256, 8, 3, k))
+    x = datagen.gaussian(200000, 50 + k).numpy()
+    ot = oracle.build_table_general(oracle.histogram(x), 256, 8, 3, k)
+    c = qlc.compress(to_dev(x), mode=mode, chunk_symbols=4096)
+    torch.cuda.synchronize()
+    assert_table_equal(c.table, ot)
+    st, obits, oindex, ototal = oracle.encode(x, ot, 4096)
+    assert c.total_bits() == ototal
+    assert np.array_equal(c.bits[:c.nbytes()].cpu().numpy(), obits)
+    out, err = qlc.decompress(c)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and np.array_equal(out.cpu().numpy(), x)
+
+
 def test_table_from_histogram_paper_rows():
     """Constructed histogram reproducing Tables 3/4 on the GPU, plus
     histograms with many ties and counts beyond 2^32."""

@@ -143,7 +143,7 @@ def test_search_costs_against_every_candidate():
     h[:4] = 0
     r2s, _ = oracle.rank(h)
     ranked = h[r2s]
-    for max_distinct in (4, 8):
+    for max_distinct in range(1, 9):
         cands = oracle.enumerate_layouts(256, 8, max_distinct)
         costs = [sum(int(ranked[r]) * (3 + w[a]) for a, (f, c) in enumerate(zip(*oracle.fill(w)[1:]))
                      for r in range(f, f + c)) for w in cands]
@@ -163,3 +163,22 @@ def test_quad_limits_distinct_lengths():
         assert ta.cost_bits <= t.cost_bits
         for mode in (oracle.MODE_PAPER_T1, oracle.MODE_PAPER_T2):
             assert t.cost_bits <= oracle.build_table(h, mode).cost_bits
+
+
+def test_distinct_caps_nest():
+    """Capping the number of distinct code lengths at k = 1..8: the capped
+    table honours the cap, its cost never rises with k, k = 4 is the quad
+    search and k = 8 the unrestricted one."""
+    rng = np.random.default_rng(13)
+    for _ in range(10):
+        h = (rng.pareto(rng.uniform(0.3, 3.0), size=256) * 1000).astype(np.uint64)
+        costs = []
+        for k in range(1, 9):
+            t = oracle.build_table_general(h, 256, 8, 3, k)
+            assert len(set(t.width.tolist())) <= k
+            costs.append(t.cost_bits)
+        assert all(a >= b for a, b in zip(costs, costs[1:]))
+        for k, mode in ((4, oracle.MODE_SEARCH_QUAD), (8, oracle.MODE_SEARCH_ANY)):
+            a, b = oracle.build_table_general(h, 256, 8, 3, k), oracle.build_table(h, mode)
+            assert list(a.width) == list(b.width) and a.cost_bits == b.cost_bits
+            assert list(a.code) == list(b.code) and list(a.len) == list(b.len)
