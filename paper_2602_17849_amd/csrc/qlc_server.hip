@@ -248,7 +248,9 @@ struct qlc_server {
   }
 
   void run() {
-    hipSetDevice(device);
+    // if the loop's thread cannot select the device, every tick fails (its
+    // requests complete with QLC_ERR_HIP) instead of running elsewhere
+    const bool dev_ok = hipSetDevice(device) == hipSuccess;
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
       uint32_t busy = 0;
@@ -272,10 +274,10 @@ struct qlc_server {
         if (nj > max_jobs_seen) max_jobs_seen = nj;
         if (busy + 1 > max_busy_seen) max_busy_seen = busy + 1;
         lk.unlock();
-        const bool ok = launch(*fs);
+        const bool ok = dev_ok && launch(*fs);
         // after a failed launch, let whatever was enqueued drain before the
         // requests' memory can be released
-        if (!ok) hipStreamSynchronize(fs->stream);
+        if (!ok) (void)hipStreamSynchronize(fs->stream);
         lk.lock();
         if (!ok) finish(*fs, false);
         continue;
@@ -295,16 +297,16 @@ struct qlc_server {
 
   void free_all() {
     for (Slot& sl : slots) {
-      if (sl.ws) hipFree(sl.ws);
-      if (sl.d_jobs) hipFree(sl.d_jobs);
-      if (sl.d_status) hipFree(sl.d_status);
-      if (sl.h_jobs) hipHostFree(sl.h_jobs);
-      if (sl.h_status) hipHostFree(sl.h_status);
-      if (sl.done) hipEventDestroy(sl.done);
-      if (sl.stream) hipStreamDestroy(sl.stream);
+      if (sl.ws) (void)hipFree(sl.ws);
+      if (sl.d_jobs) (void)hipFree(sl.d_jobs);
+      if (sl.d_status) (void)hipFree(sl.d_status);
+      if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+      if (sl.h_status) (void)hipHostFree(sl.h_status);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     slots.clear();
-    if (pool_base) hipFree(pool_base);
+    if (pool_base) (void)hipFree(pool_base);
     pool_base = nullptr;
     for (auto& kv : live) delete kv.second;
     live.clear();
