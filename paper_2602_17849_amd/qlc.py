@@ -153,10 +153,17 @@ def _check(st: int, what: str):
 
 
 def _p(t) -> int:
+    """Device address of a tensor argument (a plain int passes through).
+    The library reads flat device buffers: strided views or host tensors
+    are refused here rather than read wrongly."""
     if t is None:
         return 0
     if isinstance(t, int):
         return t
+    if not t.is_contiguous():
+        raise ValueError("libqlc arguments must be contiguous tensors")
+    if t.device.type != "cuda" and t.numel() > 0:
+        raise ValueError("libqlc arguments must be device (cuda) tensors")
     return t.data_ptr()
 
 

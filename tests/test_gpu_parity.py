@@ -246,3 +246,13 @@ def test_compress_fused(n, mode):
     out, err = qlc.decompress(c)
     torch.cuda.synchronize()
     assert int(err.item()) == 0 and np.array_equal(out.cpu().numpy(), x)
+
+
+def test_binding_refuses_strided_and_host_tensors():
+    x = torch.zeros(4096, dtype=torch.uint8, device=DEV)
+    h = torch.zeros(256, dtype=torch.int64, device=DEV)
+    ws = qlc.new_workspace(4096)
+    with pytest.raises(ValueError):
+        qlc.qlc_histogram(x[::2], h, ws)
+    with pytest.raises(ValueError):
+        qlc.qlc_histogram(x.cpu(), h, ws)
