@@ -96,7 +96,12 @@ typedef enum qlc_layout_mode {
   QLC_LAYOUT_SEARCH_DISTINCT_5 = 21,
   QLC_LAYOUT_SEARCH_DISTINCT_6 = 22,
   QLC_LAYOUT_SEARCH_DISTINCT_7 = 23,
-  QLC_LAYOUT_SEARCH_DISTINCT_8 = 24
+  QLC_LAYOUT_SEARCH_DISTINCT_8 = 24,
+  /* Four areas named by a 2-bit area code (the number of areas is another
+   * knob the Conclusion section leaves open): cheapest non-decreasing
+   * 4-tuple of widths, greedy fill, codes of 2 + width bits.  The table's
+   * areas 4..7 get width 0xFF, no ranks. */
+  QLC_LAYOUT_SEARCH_AREAS4 = 32
 } qlc_layout_mode;
 #define QLC_LAYOUT_SEARCH_DISTINCT(k) ((qlc_layout_mode)(16 + (k)))
 
@@ -107,10 +112,12 @@ typedef struct qlc_table {
                                code right aligned, len = 3 + width[area]    */
   uint8_t rank_to_sym[256]; /* decoder LUT (Table 4)                         */
   uint8_t sym_to_rank[256]; /* inverse of rank_to_sym                        */
-  uint8_t width[8];         /* suffix bits of each area, non-decreasing      */
+  uint8_t width[8];         /* suffix bits of each area, non-decreasing;
+                               0xFF in areas 4..7 of a 4-area table          */
   uint8_t offset[8];        /* rank = offset[a] + suffix                     */
   uint16_t first[8];        /* first rank of each area                       */
-  uint16_t count[8];        /* ranks held by each area, all >= 1, sum 256    */
+  uint16_t count[8];        /* ranks held by each area, >= 1 in every area
+                               used, sum 256                                 */
   uint64_t cost_bits;       /* sum of count*length over the histogram used   */
   uint32_t mode;            /* qlc_layout_mode it was built with             */
   uint32_t version;         /* QLC_ABI_VERSION                               */
@@ -261,9 +268,10 @@ qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs,
 /* Host-side persisted table form: width[8] followed by rank_to_sym[256]. */
 qlc_status qlc_table_serialize(const qlc_table* h_table,
                                uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]);
-/* Rebuild a full table on the host; rejects widths that are not
- * non-decreasing in 0..8, that leave an area empty or do not cover 256
- * ranks, and rank orders that are not a permutation. */
+/* Rebuild a full table on the host (8 areas, or 4 areas when widths 4..7
+ * are all 0xFF); rejects widths that are not non-decreasing in 0..8, that
+ * leave an area empty or do not cover 256 ranks, and rank orders that are
+ * not a permutation. */
 qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES],
                                  qlc_table* h_table);
 

@@ -322,13 +322,25 @@ qlc_status qlc_table_serialize(const qlc_table* h_table, uint8_t h_out[QLC_SERIA
 
 qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES], qlc_table* t) {
   if (!h_in || !t) return QLC_ERR_INVALID_ARGUMENT;
+  // 8 areas (3-bit area code), or 4 areas (2-bit code) with widths 4..7 = 0xFF
+  const uint32_t na = h_in[4] == 0xFFu ? 4u : 8u;
+  const uint32_t pbits = na == 4 ? 2u : 3u;
   uint32_t w[8];
-  for (int a = 0; a < 8; ++a) {
+  for (uint32_t a = 0; a < 8; ++a) {
     w[a] = h_in[a];
+    if (a >= na) {
+      if (w[a] != 0xFFu) return QLC_ERR_INVALID_ARGUMENT;
+      continue;
+    }
     if (w[a] > 8 || (a && w[a] < w[a - 1])) return QLC_ERR_INVALID_ARGUMENT;
   }
   uint32_t f = 0, first[8], count[8];
-  for (int a = 0; a < 8; ++a) {
+  for (uint32_t a = 0; a < 8; ++a) {
+    if (a >= na) {
+      first[a] = 256;
+      count[a] = 0;
+      continue;
+    }
     const uint32_t cap = 1u << w[a];
     first[a] = f;
     count[a] = cap < 256 - f ? cap : 256 - f;
@@ -342,20 +354,20 @@ qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES],
     seen[h_in[8 + r]] = true;
   }
   memset(t, 0, sizeof(*t));
-  for (int a = 0; a < 8; ++a) {
+  for (uint32_t a = 0; a < 8; ++a) {
     t->width[a] = (uint8_t)w[a];
     t->first[a] = (uint16_t)first[a];
     t->count[a] = (uint16_t)count[a];
-    t->offset[a] = (uint8_t)(w[a] == 8 ? 0 : first[a]);
+    t->offset[a] = (uint8_t)(a >= na || w[a] == 8 ? 0 : first[a]);
   }
   for (int r = 0; r < 256; ++r) {
     const uint32_t s = h_in[8 + r];
     t->rank_to_sym[r] = (uint8_t)s;
     t->sym_to_rank[s] = (uint8_t)r;
     uint32_t a = 0;
-    for (int k = 1; k < 8; ++k) a = (uint32_t)r >= first[k] ? (uint32_t)k : a;
+    for (uint32_t k = 1; k < na; ++k) a = (uint32_t)r >= first[k] ? k : a;
     const uint32_t code = (a << w[a]) | ((uint32_t)r - t->offset[a]);
-    t->enc[s] = (uint16_t)(((3 + w[a]) << 11) | code);
+    t->enc[s] = (uint16_t)(((pbits + w[a]) << 11) | code);
   }
   t->cost_bits = 0;
   t->mode = 0xFFFFFFFFu;

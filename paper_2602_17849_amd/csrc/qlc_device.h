@@ -73,6 +73,45 @@ constexpr CandidateTable make_candidate_table() {
   return t;
 }
 
+// Candidates of the 4-area layout (2-bit area code): non-decreasing
+// 4-tuples over 0..8 whose greedy fill leaves every area non-empty and
+// covers 256 ranks, in lexicographic order; widths in nibbles 0..3 (the
+// others 0xF), `ends` holds the end rank of areas 0..2.
+constexpr int kNumCandidates4 = 147;
+
+struct CandidateTable4 {
+  Candidate c[kNumCandidates4];
+  int count;
+};
+
+constexpr CandidateTable4 make_candidate_table4() {
+  CandidateTable4 t{};
+  int w[4] = {0, 0, 0, 0};
+  int n = 0;
+  while (true) {
+    uint32_t head = 0;
+    for (int a = 0; a < 3; ++a) head += 1u << w[a];
+    if (head < 256 && head + (1u << w[3]) >= 256) {
+      uint32_t pk = 0xFFFF0000u, f = 0;
+      uint64_t ends = 0;
+      for (int a = 0; a < 4; ++a) {
+        pk |= uint32_t(w[a]) << (4 * a);
+        f += 1u << w[a];
+        if (a < 3) ends |= uint64_t(f) << (8 * a);
+      }
+      if (n < kNumCandidates4) t.c[n] = Candidate{pk, uint32_t(n), ends};
+      ++n;
+    }
+    int pos = 3;
+    while (pos >= 0 && w[pos] == 8) --pos;
+    if (pos < 0) break;
+    ++w[pos];
+    for (int a = pos + 1; a < 4; ++a) w[a] = w[pos];
+  }
+  t.count = n;
+  return t;
+}
+
 // Widths of the two printed schemes (Table 1 and Table 2, "#Symbol bits").
 constexpr uint32_t kPaperT1Packed = 0x85433333u;  // 3,3,3,3,3,4,5,8
 constexpr uint32_t kPaperT2Packed = 0x85533331u;  // 1,3,3,3,3,5,5,8

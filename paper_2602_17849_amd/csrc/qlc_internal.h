@@ -26,8 +26,10 @@ constexpr int kDecThreads = 1 << kDecThreadsLog2;  // decode workgroup: one lane
 constexpr int kStageGroups = QLC_DEC_STAGE_GROUPS;  // decoded groups staged per lane (8 or 16)
 static_assert(kStageGroups == 8 || kStageGroups == 16, "stage depth");
 constexpr int kNumXcd = 8;
-// Layout modes: 0..3, or SEARCH_DISTINCT_k = 16 + k for k = 1..8.
-inline bool valid_layout_mode(uint32_t m) { return m <= 3u || (m >= 17u && m <= 24u); }            // MI355X: 8 accelerator complex dies
+// Layout modes: 0..3, SEARCH_DISTINCT_k = 16 + k for k = 1..8, SEARCH_AREAS4 = 32.
+inline bool valid_layout_mode(uint32_t m) {
+  return m <= 3u || (m >= 17u && m <= 24u) || m == 32u;
+}            // MI355X: 8 accelerator complex dies
 
 // ---- histogram kernel outputs ----------------------------------------------
 constexpr uint32_t kHistSegment = 1;     // write each segment's histogram

@@ -12,6 +12,8 @@ namespace qlc {
 __constant__ CandidateTable g_candidates = make_candidate_table();
 static_assert(make_candidate_table().count == kNumCandidates, "candidate count");
 static_assert(make_candidate_table().quad == kNumQuadCandidates, "quad candidate count");
+__constant__ CandidateTable4 g_candidates4 = make_candidate_table4();
+static_assert(make_candidate_table4().count == kNumCandidates4, "4-area candidate count");
 
 
 // ===========================================================================
@@ -85,6 +87,9 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
 
   // Layout: fixed printed widths, or the cheapest candidate (ties to the
   // smallest index = lexicographically smallest tuple).
+  // area code bits: 3 (8 areas), or 2 (4 areas) for the 4-area search
+  const uint32_t pbits = mode == QLC_LAYOUT_SEARCH_AREAS4 ? 2u : 3u;
+  const uint32_t na = 1u << pbits;
   uint32_t packed;
   if (mode == QLC_LAYOUT_PAPER_T1) {
     packed = kPaperT1Packed;
@@ -95,20 +100,24 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     // ends come with the candidate, so the eight prefix-sum reads are
     // independent.
     const uint32_t max_distinct = mode == QLC_LAYOUT_SEARCH_QUAD ? 4u
-                                  : mode == QLC_LAYOUT_SEARCH_ANY ? 8u
-                                                                  : mode - 16u;
-    const int ncand = max_distinct <= 4u ? kNumQuadCandidates : kNumCandidates;
+                                  : (mode == QLC_LAYOUT_SEARCH_ANY ||
+                                     mode == QLC_LAYOUT_SEARCH_AREAS4) ? 8u
+                                                                       : mode - 16u;
+    const Candidate* ct = na == 4 ? g_candidates4.c : g_candidates.c;
+    const int ncand = na == 4 ? kNumCandidates4
+                      : max_distinct <= 4u ? kNumQuadCandidates : kNumCandidates;
     const uint64_t pN = S.P[256];
     uint64_t best = ~0ull;
     uint32_t best_pk = 0;
     for (int i = tid; i < ncand; i += nt) {
-      const Candidate cd = g_candidates.c[i];
+      const Candidate cd = ct[i];
       if ((cd.lex >> 16) > max_distinct) continue;
-      uint64_t cost = 3 * pN;
+      uint64_t cost = pbits * pN;
       uint64_t prev = 0;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        const uint32_t e = a < 7 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
+        if ((uint32_t)a >= na) break;
+        const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
         const uint64_t pe = S.P[e];
         cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
         prev = pe;
@@ -134,11 +143,19 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     packed = S.best_packed;
   }
 
-  // Greedy fill, offsets (an 8-bit area carries the raw rank), cost.
+  // Greedy fill, offsets (an 8-bit area carries the raw rank), cost; the
+  // areas a 4-area table does not use get width 0xFF and no ranks.
   if (tid == 0) {
     uint32_t f = 0;
     uint64_t cost = 0;
     for (int a = 0; a < 8; ++a) {
+      if ((uint32_t)a >= na) {
+        S.width[a] = 0xFFu;
+        S.first[a] = 256u;
+        S.count[a] = 0u;
+        S.offset[a] = 0u;
+        continue;
+      }
       const uint32_t b = (packed >> (4 * a)) & 15u;
       const uint32_t cap = 1u << b;
       const uint32_t cnt = cap < 256u - f ? cap : 256u - f;
@@ -146,7 +163,7 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
       S.first[a] = f;
       S.count[a] = cnt;
       S.offset[a] = (b == 8) ? 0u : f;
-      cost += (uint64_t)(3 + b) * (S.P[f + cnt] - S.P[f]);
+      cost += (uint64_t)(pbits + b) * (S.P[f + cnt] - S.P[f]);
       f += cnt;
     }
     S.cost = cost;
@@ -161,7 +178,7 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     for (int k = 1; k < 8; ++k) a = (r >= S.first[k]) ? (uint32_t)k : a;
     const uint32_t b = S.width[a];
     const uint32_t code = (a << b) | (r - S.offset[a]);
-    out->enc[s] = (uint16_t)(((3 + b) << 11) | code);
+    out->enc[s] = (uint16_t)(((pbits + b) << 11) | code);
     out->rank_to_sym[s] = (uint8_t)S.r2s[s];
     out->sym_to_rank[s] = (uint8_t)r;
   }
@@ -667,9 +684,10 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   S.lut[tid] = enc_entry(e_t);
   for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) (&S.words[0][0])[w] = 0;
   __syncthreads();
-  // A table whose code lengths leave 3..11 is rejected (keeps every LDS
-  // index of the packer in bounds without per-symbol clamps).
-  if ((e_t >> 11) < 3 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.bad_table = 1;
+  // A table whose code lengths leave 2..11 is rejected: 11 keeps every LDS
+  // index of the packer in bounds without per-symbol clamps, 2 makes the 16
+  // symbols before a segment hold the 31 bits its first word may need.
+  if ((e_t >> 11) < 2 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.bad_table = 1;
   const uint32_t seg = S.seg;
   const uint32_t epoch = S.epoch;
   const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
@@ -869,23 +887,34 @@ __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __rest
 }
 
 // Code -> symbol LUT of `table` into `lut` (2048 32-bit entries, bit 15 =
-// invalid suffix) and the per-area shift table (byte a of sh_hi:sh_lo = 29 - width).
-// Any block size; the caller synchronises before using the LUT.
+// invalid suffix) and the shift table indexed by the window's top three
+// bits (byte i of sh_hi:sh_lo = 32 - prefix bits - width of the area the
+// top bits name).  A table whose areas 4..7 are marked 0xFF has a 2-bit
+// area code: top bits 2a and 2a + 1 both name area a, so the decode chain
+// is the same for both prefix widths.  Any block size; the caller
+// synchronises before using the LUT.
 __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint32_t* lut,
                               uint32_t& sh_lo, uint32_t& sh_hi) {
   sh_lo = 0;
   sh_hi = 0;
   {
+    const uint32_t p = table->width[4] == 0xFFu ? 2u : 3u;  // area code bits
+    const uint32_t na = 1u << p;
     uint32_t w[8], lo[8], off[8], first[8], cnt[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      w[a] = table->width[a] < 8 ? table->width[a] : 8u;  // keeps codes < 2048
+      const uint32_t wa = table->width[a];
+      w[a] = (uint32_t)a < na ? (wa < 8 ? wa : 8u) : 0u;  // keeps codes < 2048
       off[a] = table->offset[a];
       first[a] = table->first[a];
-      cnt[a] = table->count[a];
+      cnt[a] = (uint32_t)a < na ? table->count[a] : 0u;
       lo[a] = (uint32_t)a << w[a];
-      if (a < 4) sh_lo |= (29u - w[a]) << (8 * a);
-      else sh_hi |= (29u - w[a]) << (8 * (a - 4));
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t sft = 32u - p - w[i >> (3 - p)];
+      if (i < 4) sh_lo |= sft << (8 * i);
+      else sh_hi |= sft << (8 * (i - 4));
     }
     for (uint32_t c = threadIdx.x; c < 2048; c += blockDim.x) {
       uint32_t e = 0x8000;
@@ -1380,7 +1409,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
       }
       __syncthreads();
       const uint32_t len_t = S.enc.lut[tid] >> 16;
-      if (len_t < 3 || len_t > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
+      if (len_t < 2 || len_t > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
       const uint64_t my_bits = block_sum_u64(
           (uint64_t)load_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid]) * len_t, S.enc.red);
       const bool bad_table = S.enc.bad_table != 0;

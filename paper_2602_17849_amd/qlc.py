@@ -31,6 +31,9 @@ LAYOUT_PAPER_T1 = 2
 LAYOUT_PAPER_T2 = 3
 
 
+LAYOUT_SEARCH_AREAS4 = 32   # 2-bit area code, 4 areas
+
+
 def LAYOUT_SEARCH_DISTINCT(k: int) -> int:
     """Layout mode: cheapest tuple with at most k (1..8) distinct code lengths."""
     if not 1 <= k <= 8:

@@ -150,3 +150,23 @@ def test_server_config_errors_are_synchronous():
     assert L.qlc_server_create(None, ctypes.byref(h)) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_server_submit(None, None, None) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_server_destroy(None) == qlc.QLC_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_host_table_deserialize_four_areas(seed):
+    """A 4-area layout (widths of areas 4..7 = 0xFF) rebuilt on the host has
+    the oracle's codes, lengths (2 + width), areas and offsets; a blob with
+    only some unused areas marked is refused."""
+    rng = np.random.default_rng(100 + seed)
+    h = (rng.pareto(1.0, 256) * 100).astype(np.uint64)
+    ot = oracle.build_table_general(h, 256, 4, 2, 8)
+    blob = bytes(list(ot.width.astype(np.uint8)) + [0xFF] * 4) + bytes(ot.rank_to_sym.astype(np.uint8))
+    t = qlc.parse_table(qlc.qlc_table_deserialize(blob))
+    assert list(t["width"]) == list(ot.width) + [0xFF] * 4
+    assert list(t["first"][:4]) == list(ot.first) and list(t["count"]) == list(ot.count) + [0] * 4
+    assert list(t["offset"][:4]) == list(ot.offset)
+    assert np.array_equal(t["enc"] >> 11, ot.len) and np.array_equal(t["enc"] & 0x7FF, ot.code)
+    bad = bytearray(blob)
+    bad[7] = 8
+    with pytest.raises(qlc.QLCError):
+        qlc.qlc_table_deserialize(bytes(bad))
