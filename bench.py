@@ -359,6 +359,20 @@ def main():
         return e0.elapsed_time(e1) / reps / 1e3
 
     t_enc = timed(lambda: qlc.qlc_encode(x, table, C, bits, index, total, err, ws))
+    # bits per symbol of the tensor under every layout mode (tables built on
+    # the device from its histogram; cost_bits = sum h * len)
+    hist = torch.zeros(256, dtype=torch.int64, device=dev)
+    qlc.qlc_histogram(x, hist, ws)
+    layouts = {}
+    lt = qlc.new_table(dev)
+    named = [("SEARCH_QUAD", qlc.LAYOUT_SEARCH_QUAD), ("SEARCH_ANY", qlc.LAYOUT_SEARCH_ANY),
+             ("PAPER_T1", qlc.LAYOUT_PAPER_T1), ("PAPER_T2", qlc.LAYOUT_PAPER_T2),
+             ("SEARCH_AREAS4", qlc.LAYOUT_SEARCH_AREAS4)] + \
+        [("SEARCH_DISTINCT_%d" % k, qlc.LAYOUT_SEARCH_DISTINCT(k)) for k in (1, 2, 3)]
+    for name, mode in named:
+        qlc.qlc_table_from_histogram(hist, mode, lt)
+        torch.cuda.synchronize()
+        layouts[name] = round(qlc.parse_table(lt)["cost_bits"] / n, 5)
     t_tab = timed(lambda: qlc.qlc_build_table(x, qlc.LAYOUT_SEARCH_QUAD, table, ws))
     torch.cuda.synchronize()
     tb = int(total.item())
@@ -393,6 +407,7 @@ def main():
         "compressibility": round((8 - L) / 8, 5),
         "compressibility_with_index_and_table": round(
             1 - (stream_bytes + index_bytes + 264) / n, 5),
+        "bits_per_symbol_by_layout": layouts,
         "roofline": {"kernel": "k_decode", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
