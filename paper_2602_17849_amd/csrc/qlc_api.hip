@@ -11,20 +11,29 @@ namespace qlc {
 namespace {
 
 constexpr int kMaxDevices = 64;
-int g_num_cus[kMaxDevices];
-std::once_flag g_cu_once[kMaxDevices];
+// Per device, queried once: compute units and the resident workgroups per
+// CU of the two persistent kernels (the occupancy query costs microseconds
+// of host time, which a small batched call would otherwise pay every time).
+struct DeviceInfo {
+  int cus;
+  int enc_blocks_per_cu;
+  int dec_blocks_per_cu;
+};
+DeviceInfo g_dev_info[kMaxDevices];
+std::once_flag g_dev_once[kMaxDevices];
 
-int device_cus() {
+const DeviceInfo& device_info() {
+  static const DeviceInfo fallback = {256, 1, 1};
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
-  std::call_once(g_cu_once[dev], [dev] {
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return fallback;
+  std::call_once(g_dev_once[dev], [dev] {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    g_num_cus[dev] = cus;
+    g_dev_info[dev] = {cus, batched_blocks_per_cu(false), batched_blocks_per_cu(true)};
   });
-  return g_num_cus[dev];
+  return g_dev_info[dev];
 }
 
 bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
@@ -108,7 +117,8 @@ bool batch_tuning(const qlc_batch_tuning* t, uint32_t* log2_seg, uint32_t* lag, 
 
 uint32_t persistent_grid(bool decode, uint32_t requested) {
   if (requested) return requested;
-  const uint32_t g = (uint32_t)(device_cus() * batched_blocks_per_cu(decode));
+  const DeviceInfo& d = device_info();
+  const uint32_t g = (uint32_t)(d.cus * (decode ? d.dec_blocks_per_cu : d.enc_blocks_per_cu));
   return g ? g : 1;
 }
 
