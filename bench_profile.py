@@ -17,6 +17,9 @@ hash.  DIR defaults to profile_runs/ (raw rocprofv3 output, not committed).
     python3 bench_profile.py copy     # the calibration workload itself
     python3 bench_profile.py batched [--tuning C,LOG2_SEGMENT,LAG] [--out DIR]
         # kernel durations of the batched form on the 1152-shard workload
+    python3 bench_profile.py sq [--chunk C] [--out DIR]
+        # SQ issue / stall counters of k_decode on the 256 MiB tensor (two
+        # --pmc passes of at most eight SQ counters each)
 """
 from __future__ import annotations
 
@@ -187,9 +190,72 @@ def collect_batched(tuning):
     print("\n".join(lines))
 
 
+SQ_PASSES = (
+    ["SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+     "SQ_INSTS_LDS", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_ANY"],
+    ["SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT",
+     "SQ_LDS_IDX_ACTIVE", "SQ_LDS_ADDR_CONFLICT", "SQ_INSTS_VMEM_RD", "SQ_ACTIVE_INST_VMEM"],
+)
+
+
+def collect_sq(chunk, kernel="k_decode"):
+    """Per-launch SQ counters of one kernel, summed over the device, and
+    per-wave figures derived from them (wave-cycle counters are in units of
+    four cycles)."""
+    os.makedirs(OUT, exist_ok=True)
+    bench = ["python3", "bench.py", "--steps", "3", "--warmup", "1", "--no-cpu-baseline",
+             "--no-batched", "--no-serving", "--chunk", str(chunk)]
+    vals, cmds = {}, []
+    for i, ctrs in enumerate(SQ_PASSES):
+        d = os.path.join(OUT, "sq%d" % (i + 1))
+        cmd = ["rocprofv3", "--pmc"] + ctrs + ["--output-format", "csv", "-d", d,
+                                               "-o", "sq%d" % (i + 1), "--"] + bench
+        cmds.append(cmd)
+        run(cmd, d + ".log")
+        per = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if short(r["Kernel_Name"]) != kernel:
+                    continue
+                key = (r["Counter_Name"], r["Dispatch_Id"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        for (c, _), v in per.items():
+            vals.setdefault(c, []).append(v)
+    v = {c: sum(x) / len(x) for c, x in vals.items()}
+    waves = v.get("SQ_WAVES", 0.0) or 1.0
+    life = v.get("SQ_WAVE_CYCLES", 0.0) / waves or 1.0
+    lines = ["# SQ counters of %s on the single 256 MiB tensor (C = %d)" % (kernel, chunk), "",
+             "Commands (run from the repository root): " +
+             "; ".join("`%s`" % " ".join(c) for c in cmds), "",
+             "| counter | per launch (device total) | per wave | % of wave lifetime |",
+             "|---|---|---|---|"]
+    for c in SQ_PASSES[0] + SQ_PASSES[1]:
+        if c not in v:
+            continue
+        pw = v[c] / waves
+        frac = ("%.1f" % (100.0 * pw / life)) if c.startswith(("SQ_ACTIVE", "SQ_WAIT")) else ""
+        lines.append("| %s | %.4g | %.4g | %s |" % (c, v[c], pw, frac))
+    if v.get("SQ_LDS_IDX_ACTIVE"):
+        lines += ["", "LDS bank-conflict stall cycles / LDS indexed-active cycles: %.3f" % (
+            v.get("SQ_LDS_BANK_CONFLICT", 0.0) / v["SQ_LDS_IDX_ACTIVE"])]
+    sys.path.insert(0, ROOT)
+    from bench import kernel_source_hash
+    lines += ["", "Kernel source hash: %s" % kernel_source_hash()]
+    with open(os.path.join(OUT, "%s_sq_counters_256MiB.md" % kernel), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "copy":
         copy_workload()
+    elif len(sys.argv) > 1 and sys.argv[1] == "sq":
+        if "--out" in sys.argv:
+            OUT = sys.argv[sys.argv.index("--out") + 1]
+        chunk = int(sys.argv[sys.argv.index("--chunk") + 1]) if "--chunk" in sys.argv else 2048
+        os.environ["TMPDIR"] = "/tmp"
+        os.chdir(ROOT)
+        collect_sq(chunk)
     elif len(sys.argv) > 1 and sys.argv[1] == "batched":
         if "--out" in sys.argv:
             OUT = sys.argv[sys.argv.index("--out") + 1]
