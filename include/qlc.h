@@ -151,12 +151,17 @@ qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out,
  * aligned) is read and written by the last workgroup on `stream`, so calls
  * on one stream accumulate in order; the caller zeroes it before the first
  * call.  Same argument rules and errors as qlc_histogram.  Feeding the sum
- * to qlc_table_from_histogram gives one table for every tensor summed. */
+ * to qlc_table_from_histogram gives one table for every tensor summed
+ * (while the sum stays below 2^48 symbols). */
 qlc_status qlc_histogram_accumulate(const uint8_t* in, uint64_t n, uint64_t* hist_inout,
                                     void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Steps 2-4 (Implementation section, Tables 1-4): build *table_out from a
- * device histogram of 256 uint64 counts. */
+ * device histogram of 256 uint64 counts.  The counts must sum to less than
+ * 2^48 (every single-call histogram does: n < 2^36); from a larger sum the
+ * table comes out marked unusable (every code length 0, every width 0xFF),
+ * and an encode with it fails with QLC_ERR_INVALID_ARGUMENT.  Scale such a
+ * histogram down first. */
 qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
                                     qlc_table* table_out, hipStream_t stream);
 

@@ -22,10 +22,12 @@ static_assert(make_candidate_table4().count == kNumCandidates4, "4-area candidat
 // ===========================================================================
 struct TableSmem {
   uint64_t h[256];
+  uint64_t key[256];        // count << 8 | (255 - symbol): unique sort keys
   uint64_t P[257];          // P[r] = sum of the counts of ranks < r
   uint64_t wave_min[16];
-  uint32_t best_packed;
+  uint32_t wave_pk[16];     // layout of each wave's cheapest candidate
   uint32_t rank[256];       // symbol -> rank
+  uint32_t rpart[4 * 256];  // partial ranks, one row per quarter of the keys
   uint32_t r2s[256];        // rank -> symbol
   uint32_t width[8], first[8], count[8], offset[8];
   uint64_t cost;
@@ -40,30 +42,38 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   qlc_table* out = &S.stage;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  for (int s = tid; s < 256; s += nt) S.h[s] = h_in[s];
-  __syncthreads();
+  int big = 0;  // a count of 2^48 or more
+  for (int s = tid; s < 256; s += nt) {
+    const uint64_t c = h_in[s];
+    S.h[s] = c;
+    S.key[s] = (c << 8) | (uint64_t)(255 - s);
+    big |= (c >> 48) != 0 ? 1 : 0;
+  }
+  big = __syncthreads_or(big);
 
   // Rank = number of symbols that sort before s: larger count, or equal
-  // count and smaller symbol value.  Every wave holds all 256 counts (four
-  // per lane) and ranks its share of the symbols with ballots: one compare
-  // per held count and a population count per symbol.
+  // count and smaller symbol value, i.e. the number of larger keys (counts
+  // are below 2^48, so count << 8 loses nothing).  Each (symbol, part) pair
+  // counts the larger keys in its part of the 256 keys, read as LDS
+  // broadcasts (two or three VALU ops per key, no cross-lane traffic); a
+  // workgroup of 256 * parts threads covers all pairs in one pass.
   {
-    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    uint64_t hu[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) hu[k] = S.h[lane + 64 * k];
-    for (int s = wave; s < 256; s += nw) {
-      const uint64_t hs = S.h[s];
+    const int parts = nt >= 1024 ? 4 : (nt >= 512 ? 2 : 1);
+    const int span = 256 / parts;
+    for (int i = tid; i < 256 * parts; i += nt) {
+      const int s = i & 255, p = i >> 8;
+      const uint64_t ks = S.key[s];
       uint32_t r = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int u = lane + 64 * k;
-        r += (uint32_t)__popcll(__ballot((hu[k] > hs) || (hu[k] == hs && u < s)));
-      }
-      if (lane == 0) {
-        S.rank[s] = r;
-        S.r2s[r] = s;
-      }
+#pragma unroll 16
+      for (int u = p * span; u < (p + 1) * span; ++u) r += S.key[u] > ks ? 1u : 0u;
+      S.rpart[i] = r;
+    }
+    __syncthreads();
+    for (int s = tid; s < 256; s += nt) {
+      uint32_t r = 0;
+      for (int p = 0; p < parts; ++p) r += S.rpart[p * 256 + s];
+      S.rank[s] = r;
+      S.r2s[r] = s;
     }
   }
   __syncthreads();
@@ -109,66 +119,99 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     const uint64_t pN = S.P[256];
     uint64_t best = ~0ull;
     uint32_t best_pk = 0;
-    for (int i = tid; i < ncand; i += nt) {
-      const Candidate cd = ct[i];
-      if ((cd.lex >> 16) > max_distinct) continue;
-      uint64_t cost = pbits * pN;
-      uint64_t prev = 0;
+    // Four candidates per thread and step, all four loaded before any is
+    // costed, so the constant-table loads overlap.
+    constexpr int kCandStep = 4;
+    for (int i0 = tid; i0 < ncand; i0 += kCandStep * nt) {
+      Candidate cds[kCandStep];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        if ((uint32_t)a >= na) break;
-        const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
-        const uint64_t pe = S.P[e];
-        cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
-        prev = pe;
+      for (int u = 0; u < kCandStep; ++u) {
+        const int i = i0 + u * nt;
+        cds[u] = ct[i < ncand ? i : 0];
       }
-      const uint64_t key = (cost << 12) | (uint64_t)(cd.lex & 0xFFFFu);
-      if (key < best) {
-        best = key;
-        best_pk = cd.packed;
+#pragma unroll
+      for (int u = 0; u < kCandStep; ++u) {
+        const Candidate& cd = cds[u];
+        if (i0 + u * nt >= ncand || (cd.lex >> 16) > max_distinct) continue;
+        uint64_t cost = pbits * pN;
+        uint64_t prev = 0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          if ((uint32_t)a >= na) break;
+          const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
+          const uint64_t pe = S.P[e];
+          cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
+          prev = pe;
+        }
+        const uint64_t key = (cost << 12) | (uint64_t)(cd.lex & 0xFFFFu);
+        if (key < best) {
+          best = key;
+          best_pk = cd.packed;
+        }
       }
     }
+    // keys are unique (lex differs), so exactly one lane of a wave holds
+    // the wave's minimum and records its layout; every thread then picks
+    // the smallest of the wave minima (a wave without candidates reports
+    // ~0, which never wins: every mode has at least one candidate)
     const uint64_t wmin = wave_min_u64(best);
     if ((tid & 63) == 0) S.wave_min[tid >> 6] = wmin;
+    if (best == wmin && best != ~0ull) S.wave_pk[tid >> 6] = best_pk;
     __syncthreads();
-    if (tid == 0) {
-      uint64_t m = S.wave_min[0];
-      for (int w = 1; w < nt / 64; ++w) m = S.wave_min[w] < m ? S.wave_min[w] : m;
-      S.wave_min[0] = m;
+    uint64_t m = S.wave_min[0];
+    int wb = 0;
+    for (int w = 1; w < nt / 64; ++w) {
+      if (S.wave_min[w] < m) {
+        m = S.wave_min[w];
+        wb = w;
+      }
     }
-    __syncthreads();
-    // keys are unique (lex differs), so exactly one thread holds the minimum
-    if (best == S.wave_min[0]) S.best_packed = best_pk;
-    __syncthreads();
-    packed = S.best_packed;
+    packed = S.wave_pk[wb];
   }
 
   // Greedy fill, offsets (an 8-bit area carries the raw rank), cost; the
-  // areas a 4-area table does not use get width 0xFF and no ranks.
-  if (tid == 0) {
+  // areas a 4-area table does not use get width 0xFF and no ranks.  Lane a
+  // of wave 0 fills area a: its first rank is the capacity of the areas
+  // before it, capped at 256.
+  if (tid < 64) {
+    const uint32_t a = (uint32_t)tid & 7u;
     uint32_t f = 0;
-    uint64_t cost = 0;
-    for (int a = 0; a < 8; ++a) {
-      if ((uint32_t)a >= na) {
-        S.width[a] = 0xFFu;
-        S.first[a] = 256u;
-        S.count[a] = 0u;
-        S.offset[a] = 0u;
-        continue;
-      }
+    for (uint32_t k = 0; k < a && k < na; ++k) {
+      const uint32_t c = f + (1u << ((packed >> (4 * k)) & 15u));
+      f = c < 256u ? c : 256u;
+    }
+    uint64_t term = 0;
+    uint32_t w = 0xFFu, first = 256u, cnt = 0u, off = 0u;
+    if (a < na) {
       const uint32_t b = (packed >> (4 * a)) & 15u;
       const uint32_t cap = 1u << b;
-      const uint32_t cnt = cap < 256u - f ? cap : 256u - f;
-      S.width[a] = b;
-      S.first[a] = f;
-      S.count[a] = cnt;
-      S.offset[a] = (b == 8) ? 0u : f;
-      cost += (uint64_t)(pbits + b) * (S.P[f + cnt] - S.P[f]);
-      f += cnt;
+      cnt = cap < 256u - f ? cap : 256u - f;
+      w = b;
+      first = f;
+      off = (b == 8) ? 0u : f;
+      term = (uint64_t)(pbits + b) * (S.P[f + cnt] - S.P[f]);
     }
-    S.cost = cost;
+    // sum of the eight lanes' terms (lanes 8.. repeat lanes 0..7)
+#pragma unroll
+    for (int d = 1; d < 8; d <<= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)term, d, 64);
+      const uint32_t hi = __shfl_xor((uint32_t)(term >> 32), d, 64);
+      term += ((uint64_t)hi << 32) | lo;
+    }
+    if (tid < 8) {
+      S.width[a] = w;
+      S.first[a] = first;
+      S.count[a] = cnt;
+      S.offset[a] = off;
+    }
+    if (tid == 0) S.cost = term;
   }
   __syncthreads();
+
+  // Counts must sum below 2^48 (so that the rank keys and the search keys
+  // are exact); a larger histogram yields a table marked unusable: every
+  // code length 0 and every width 0xFF, which the encoders reject.
+  const bool unusable = big != 0 || (S.P[256] >> 48) != 0;
 
   // Encoder LUT (Table 3), indexed by input symbol.
   for (int s = tid; s < 256; s += nt) {
@@ -178,18 +221,18 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     for (int k = 1; k < 8; ++k) a = (r >= S.first[k]) ? (uint32_t)k : a;
     const uint32_t b = S.width[a];
     const uint32_t code = (a << b) | (r - S.offset[a]);
-    out->enc[s] = (uint16_t)(((pbits + b) << 11) | code);
+    out->enc[s] = unusable ? (uint16_t)0 : (uint16_t)(((pbits + b) << 11) | code);
     out->rank_to_sym[s] = (uint8_t)S.r2s[s];
     out->sym_to_rank[s] = (uint8_t)r;
   }
   if (tid < 8) {
-    out->width[tid] = (uint8_t)S.width[tid];
-    out->offset[tid] = (uint8_t)S.offset[tid];
-    out->first[tid] = (uint16_t)S.first[tid];
-    out->count[tid] = (uint16_t)S.count[tid];
+    out->width[tid] = unusable ? (uint8_t)0xFFu : (uint8_t)S.width[tid];
+    out->offset[tid] = unusable ? (uint8_t)0u : (uint8_t)S.offset[tid];
+    out->first[tid] = unusable ? (uint16_t)256u : (uint16_t)S.first[tid];
+    out->count[tid] = unusable ? (uint16_t)0u : (uint16_t)S.count[tid];
   }
   if (tid == 0) {
-    out->cost_bits = S.cost;
+    out->cost_bits = unusable ? ~0ull : S.cost;
     out->mode = mode;
     out->version = QLC_ABI_VERSION;
   }

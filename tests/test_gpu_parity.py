@@ -311,6 +311,32 @@ def test_bad_table_rejected(sym, length):
     assert int(b.err[0]) == qlc.QLC_ERR_INVALID_ARGUMENT and int(b.err[1]) == 0
 
 
+@pytest.mark.parametrize("case", ["one_count", "sum"])
+def test_table_from_oversized_histogram_is_unusable(case):
+    """Counts summing to 2^48 or more (or any count that large) give a table
+    marked unusable (every code length 0, every width 0xFF), which the
+    encoder rejects; a sum just below 2^48 still gives the oracle's table."""
+    hh = np.ones(256, np.uint64)
+    if case == "one_count":
+        hh[3] = np.uint64(1) << np.uint64(50)
+    else:
+        hh[:] = np.uint64(1) << np.uint64(41)          # 256 * 2^41 = 2^49
+    t = qlc.new_table()
+    qlc.qlc_table_from_histogram(to_dev(hh.astype(np.int64)), qlc.LAYOUT_SEARCH_QUAD, t)
+    torch.cuda.synchronize()
+    raw = qlc.parse_table(t)
+    assert all(v == 0 for v in raw["enc"]) and all(w == 0xFF for w in raw["width"])
+    x = datagen.gaussian(100_000, 14).numpy()
+    err = gpu_encode(to_dev(x), t, 4096)[0]
+    assert err == qlc.QLC_ERR_INVALID_ARGUMENT
+    # just below the limit: the exact table
+    below = np.ones(256, np.uint64)
+    below[7] = (np.uint64(1) << np.uint64(48)) - np.uint64(256)   # sum = 2^48 - 1
+    qlc.qlc_table_from_histogram(to_dev(below.astype(np.int64)), qlc.LAYOUT_SEARCH_QUAD, t)
+    torch.cuda.synchronize()
+    assert_table_equal(t, oracle.build_table(below, qlc.LAYOUT_SEARCH_QUAD))
+
+
 def test_deterministic_repeat():
     x = to_dev(datagen.gaussian(1 << 20, 9).numpy())
     t = gpu_table(x, 0)
