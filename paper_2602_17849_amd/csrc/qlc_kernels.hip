@@ -9,6 +9,29 @@
 
 namespace qlc {
 
+// Device global memory.  The hot loads and stores of the job buffers go
+// through pointers qualified with it: a batched kernel reads a job's
+// pointers from the job array, and through such generic pointers the
+// compiler would emit flat accesses, which also count against the LDS wait
+// counter (every wait for LDS results would then wait for them too).
+#define QLC_GLOBAL __attribute__((address_space(1)))
+typedef unsigned int GVec4 __attribute__((ext_vector_type(4)));
+typedef unsigned int GVec2 __attribute__((ext_vector_type(2)));
+
+// 16-byte element i of a global array, as a uint4.
+__device__ __forceinline__ uint4 gload_u4(const QLC_GLOBAL GVec4* p, uint64_t i) {
+  const GVec4 v = p[i];
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// 8 bytes at an 8-byte aligned global address.
+__device__ __forceinline__ void gstore_u2(QLC_GLOBAL uint8_t* p, uint2 v) {
+  GVec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(QLC_GLOBAL GVec2*)p = w;
+}
+
 __constant__ CandidateTable g_candidates = make_candidate_table();
 static_assert(make_candidate_table().count == kNumCandidates, "candidate count");
 static_assert(make_candidate_table().quad == kNumQuadCandidates, "quad candidate count");
@@ -290,21 +313,22 @@ __device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uin
                                              uint64_t seg1, uint32_t* sub, uint32_t tid) {
   const uint32_t nt = blockDim.x;
   const uint32_t copy = tid & (kHistCopies - 1);
-  const uint4* vin = reinterpret_cast<const uint4*>(in);
+  const QLC_GLOBAL GVec4* vin = (const QLC_GLOBAL GVec4*)in;
   const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
   uint64_t i = v0 + tid;
   if (i + 3 * nt < v1) {
     // the next four vectors are loaded before the current four are counted
-    uint4 a = vin[i], b = vin[i + nt], c = vin[i + 2 * nt], d = vin[i + 3 * nt];
+    uint4 a = gload_u4(vin, i), b = gload_u4(vin, i + nt);
+    uint4 c = gload_u4(vin, i + 2 * nt), d = gload_u4(vin, i + 3 * nt);
     for (;;) {
       const uint64_t nx = i + 4 * nt;
       const bool more = nx + 3 * nt < v1;
       uint4 na = a, nb = b, nc = c, nd = d;
       if (more) {
-        na = vin[nx];
-        nb = vin[nx + nt];
-        nc = vin[nx + 2 * nt];
-        nd = vin[nx + 3 * nt];
+        na = gload_u4(vin, nx);
+        nb = gload_u4(vin, nx + nt);
+        nc = gload_u4(vin, nx + 2 * nt);
+        nd = gload_u4(vin, nx + 3 * nt);
       }
       hist_add_vec(sub, a, copy);
       hist_add_vec(sub, b, copy);
@@ -318,9 +342,9 @@ __device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uin
       d = nd;
     }
   }
-  for (; i < v1; i += nt) hist_add_vec(sub, vin[i], copy);
+  for (; i < v1; i += nt) hist_add_vec(sub, gload_u4(vin, i), copy);
   for (uint64_t j = (v1 << 4) + tid; j < seg1; j += nt)  // ragged tail of the input
-    atomicAdd(&sub[((uint32_t)in[j] << 5) | copy], 1u);
+    atomicAdd(&sub[((uint32_t)((const QLC_GLOBAL uint8_t*)in)[j] << 5) | copy], 1u);
 }
 
 // Per-bin total of the 32 copies (thread t < 256 sums bin t).
@@ -461,7 +485,7 @@ __device__ __forceinline__ uint32_t pair_len(uint32_t e0, uint32_t e1) {
 
 // State of a segment's encode carried from tile to tile.
 struct EncSeg {
-  const uint8_t* in;
+  const QLC_GLOBAL uint8_t* in;
   uint64_t seg1;
   uint64_t R;                        // global bit offset of the current tile
   uint64_t seg_w0;                   // the segment's first stream word
@@ -470,7 +494,7 @@ struct EncSeg {
   uint32_t log2_chunk;
   bool last_seg;
   __amdgpu_buffer_rsrc_t out_rsrc;   // stream words from seg_w0 on, clipped at cap_words
-  uint64_t* index_out;
+  QLC_GLOBAL uint64_t* index_out;
   uint4 nx0, nx1;                    // the next full tile's input (prefetched)
   uint32_t buf;                      // word buffer of the current tile
 };
@@ -493,9 +517,9 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
     const uint4 v0 = E.nx0, v1 = E.nx1;
     {  // prefetch the next tile (this one again when no whole tile follows)
       const uint64_t nt = (t0 + 2 * kEncTile <= E.seg1) ? t0 + kEncTile : t0;
-      const uint4* p = reinterpret_cast<const uint4*>(E.in + nt + (uint64_t)tid * 16);
-      E.nx0 = p[0];
-      E.nx1 = p[kEncThreads];
+      const QLC_GLOBAL GVec4* p = (const QLC_GLOBAL GVec4*)(E.in + nt + (uint64_t)tid * 16);
+      E.nx0 = gload_u4(p, 0);
+      E.nx1 = gload_u4(p, kEncThreads);
     }
     const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
@@ -630,14 +654,14 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
     S.words[0][0] = w0;
   }
   EncSeg E;
-  E.in = in;
+  E.in = (const QLC_GLOBAL uint8_t*)in;
   E.seg1 = seg1;
   E.R = G;
   E.cap_words = cap_words;
   E.cmask = (1ull << log2_chunk) - 1;
   E.log2_chunk = log2_chunk;
   E.last_seg = last_seg;
-  E.index_out = index_out;
+  E.index_out = (QLC_GLOBAL uint64_t*)index_out;
   // Output through a buffer resource based at the segment's first word
   // (segment-relative offsets stay far below 2^32): stores at or past
   // cap_words are dropped by the hardware.
@@ -650,9 +674,9 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
   E.nx0 = make_uint4(0, 0, 0, 0);
   E.nx1 = E.nx0;
   if (seg0 + kEncTile <= seg1) {
-    const uint4* p = reinterpret_cast<const uint4*>(in + seg0 + (uint64_t)tid * 16);
-    E.nx0 = p[0];
-    E.nx1 = p[kEncThreads];
+    const QLC_GLOBAL GVec4* p = (const QLC_GLOBAL GVec4*)(E.in + seg0 + (uint64_t)tid * 16);
+    E.nx0 = gload_u4(p, 0);
+    E.nx1 = gload_u4(p, kEncThreads);
   }
   uint64_t t0 = seg0;
   for (; t0 + kEncTile <= seg1; t0 += kEncTile) cap |= encode_tile<true>(E, t0, S, tid);
@@ -673,13 +697,13 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
   __syncthreads();
   const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
-  const uint4* vin = reinterpret_cast<const uint4*>(in);
+  const QLC_GLOBAL GVec4* vin = (const QLC_GLOBAL GVec4*)in;
   const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;
   uint32_t s = 0;
   uint64_t i = v0 + tid;
   for (; i + 3 * kHistThreads < v1; i += 4 * kHistThreads) {
-    const uint4 a = vin[i], b = vin[i + kHistThreads];
-    const uint4 c = vin[i + 2 * kHistThreads], d = vin[i + 3 * kHistThreads];
+    const uint4 a = gload_u4(vin, i), b = gload_u4(vin, i + kHistThreads);
+    const uint4 c = gload_u4(vin, i + 2 * kHistThreads), d = gload_u4(vin, i + 3 * kHistThreads);
     const uint32_t w[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
                             c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
 #pragma unroll
@@ -688,7 +712,7 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
            len[w[k] >> 24];
   }
   for (; i < v1; i += kHistThreads) {
-    const uint4 a = vin[i];
+    const uint4 a = gload_u4(vin, i);
     const uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -979,9 +1003,11 @@ __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ tabl
 // LUT.  Returns true in a lane whose chunk is corrupt (or whose index
 // entries are inconsistent).
 __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, uint64_t total,
-                             const uint64_t* __restrict__ index, uint32_t log2_chunk, uint64_t n,
-                             uint8_t* __restrict__ out, uint64_t grp, uint32_t sh_lo,
+                             const uint64_t* __restrict__ index_p, uint32_t log2_chunk, uint64_t n,
+                             uint8_t* __restrict__ out_p, uint64_t grp, uint32_t sh_lo,
                              uint32_t sh_hi, DecSmem& S, uint32_t tid) {
+  const QLC_GLOBAL uint64_t* __restrict__ index = (const QLC_GLOBAL uint64_t*)index_p;
+  QLC_GLOBAL uint8_t* __restrict__ out = (QLC_GLOBAL uint8_t*)out_p;
   const uint32_t lane = tid & 63;
   const uint32_t C = 1u << log2_chunk;
   const uint64_t nchunks = (n + C - 1) >> log2_chunk;
@@ -1050,7 +1076,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     uint32_t sba = 0, sbb = 0;
     bool va = false, vb = false;
     uint2* stage = S.stage + tid * kStageGroups;
-    uint8_t* o = out + (j << log2_chunk);
+    QLC_GLOBAL uint8_t* o = out + (j << log2_chunk);
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
 
@@ -1088,7 +1114,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       constexpr uint32_t R = kStageGroups;      // lanes per output run
       constexpr uint32_t kRuns = 64 / R;        // runs per store instruction
       const uint32_t part = lane % R;
-      uint8_t* obase = out + ((j_wave + lane / R) << log2_chunk) + part * 8u;
+      QLC_GLOBAL uint8_t* obase = out + ((j_wave + lane / R) << log2_chunk) + part * 8u;
       // Software pipelined: the next group's window is read right after the
       // current chain (and after the ring write it may depend on), so its
       // LDS latency overlaps the current group's LUT gathers and packing.
@@ -1127,7 +1153,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
         for (uint32_t k = 0; k < R; ++k) {
           const uint32_t stid = (tid & ~63u) | (lane / R + kRuns * k);
           const uint2 v = S.stage[stid * R + stage_slot(g0 + part, stid)];
-          *reinterpret_cast<uint2*>(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8) = v;
+          gstore_u2(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8, v);
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -1155,7 +1181,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
           const uint64_t jj = grp * kDecThreads + stid;
           const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
           if (g + part < ngrp)
-            *reinterpret_cast<uint2*>(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8) = v;
+            gstore_u2(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8, v);
         }
         __builtin_amdgcn_wave_barrier();
       }
