@@ -208,7 +208,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def run_serving(dev, duration_s=10.0, chunk=1024, log2_segment=16, budget=32 << 30):
+def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 30):
     """The serving loop (qlc_server_*) under Poisson arrivals, then the same
     requests submitted at once (saturation)."""
     import torch
