@@ -17,9 +17,9 @@ hash.  DIR defaults to profile_runs/ (raw rocprofv3 output, not committed).
     python3 bench_profile.py copy     # the calibration workload itself
     python3 bench_profile.py batched [--tuning C,LOG2_SEGMENT,LAG] [--out DIR]
         # kernel durations of the batched form on the 1152-shard workload
-    python3 bench_profile.py sq [--chunk C] [--out DIR]
-        # SQ issue / stall counters of k_decode on the 256 MiB tensor (two
-        # --pmc passes of at most eight SQ counters each)
+    python3 bench_profile.py sq [--kernel K] [--chunk C] [--out DIR]
+        # SQ issue / stall counters of kernel K (default k_decode) on the
+        # 256 MiB tensor (two --pmc passes of at most eight SQ counters each)
 """
 from __future__ import annotations
 
@@ -255,7 +255,8 @@ if __name__ == "__main__":
         chunk = int(sys.argv[sys.argv.index("--chunk") + 1]) if "--chunk" in sys.argv else 2048
         os.environ["TMPDIR"] = "/tmp"
         os.chdir(ROOT)
-        collect_sq(chunk)
+        kernel = sys.argv[sys.argv.index("--kernel") + 1] if "--kernel" in sys.argv else "k_decode"
+        collect_sq(chunk, kernel)
     elif len(sys.argv) > 1 and sys.argv[1] == "batched":
         if "--out" in sys.argv:
             OUT = sys.argv[sys.argv.index("--out") + 1]
