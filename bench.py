@@ -293,7 +293,7 @@ def main():
                     help="C,LOG2_SEGMENT,LAG for the batched form instead of the autotuner")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(each tensor shard is compressed independently on its own GPU)", file=sys.stderr)
         sys.exit(2)
 
