@@ -740,7 +740,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     uint32_t nseg) {
   __shared__ EncSmem S;
   const uint32_t tid = threadIdx.x;
-  const uint32_t lane = tid & 63, wave = tid >> 6;
   if (tid == 0) {
     S.seg = atomic_add_u32(&hdr->enc_ticket, 1u);
     S.epoch = load_relaxed_u32(&hdr->enc_epoch) & kEpochMask;
