@@ -95,6 +95,10 @@ def test_host_table_deserialize_rejects_invalid():
             qlc.qlc_table_deserialize(bytes(w) + perm)
     with pytest.raises(qlc.QLCError):
         qlc.qlc_table_deserialize(bytes([3, 3, 3, 3, 3, 4, 5, 8]) + bytes([0]) + perm[1:255] + bytes([0]))
+    # the table the device builds from a histogram summing to 2^48 or more
+    # (every width 0xFF) serializes to a blob that does not load back
+    with pytest.raises(qlc.QLCError):
+        qlc.qlc_table_deserialize(bytes([0xFF] * 8) + perm)
 
 
 def test_struct_layouts_match_the_header():
