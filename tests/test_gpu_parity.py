@@ -337,6 +337,56 @@ def test_table_from_oversized_histogram_is_unusable(case):
     assert_table_equal(t, oracle.build_table(below, qlc.LAYOUT_SEARCH_QUAD))
 
 
+def _small_float_codes(n, mant_bits, exp_bits, seed):
+    """Codes of a small sign/exponent/mantissa float type (one code per byte,
+    values below 2^(1 + exp_bits + mant_bits)) for Laplace(0, 1) samples,
+    rounded to the nearest representable magnitude."""
+    rng = np.random.default_rng(seed)
+    v = rng.laplace(0.0, 1.0, n)
+    mags = []
+    for e in range(1 << exp_bits):
+        for m in range(1 << mant_bits):
+            frac = m / (1 << mant_bits)
+            mags.append(frac if e == 0 else (1 + frac) * 2.0 ** (e - 1))
+    mags = np.array(mags)
+    idx = np.abs(np.abs(v)[:, None] - mags[None, :]).argmin(1)
+    half = len(mags)
+    return (idx + half * (v < 0)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("fmt", [(1, 2), (2, 3)])        # e2m1 (16 codes), e3m2 (64 codes)
+@pytest.mark.parametrize("mode", [qlc.LAYOUT_SEARCH_QUAD, qlc.LAYOUT_SEARCH_ANY,
+                                  qlc.LAYOUT_SEARCH_AREAS4])
+def test_small_alphabets_one_code_per_byte(fmt, mode):
+    """Narrower float types (4-bit e2m1, 6-bit e3m2) stored one code per
+    byte: the unused byte values have zero counts and rank last, so every
+    layout mode applies unchanged; table, stream and index equal the
+    oracle's and the decode restores every code."""
+    mant, exp = fmt
+    x = _small_float_codes(200003, mant, exp, seed=21 + mant)
+    assert int(x.max()) < (1 << (1 + exp + mant))
+    h = oracle.histogram(x)
+    if mode == qlc.LAYOUT_SEARCH_AREAS4:
+        ot = oracle.build_table_general(h, 256, 4, 2, 8)
+    else:
+        ot = oracle.build_table(h, mode)
+    c = qlc.compress(to_dev(x), mode=mode, chunk_symbols=1024)
+    torch.cuda.synchronize()
+    assert int(c.err.item()) == 0
+    if mode == qlc.LAYOUT_SEARCH_AREAS4:
+        _assert_areas4_table(c.table, ot)
+    else:
+        assert_table_equal(c.table, ot)
+    st, obits, oindex, ototal = oracle.encode(x, ot, 1024)
+    assert c.total_bits() == ototal
+    assert np.array_equal(c.bits[:c.nbytes()].cpu().numpy(), obits)
+    k = qlc.qlc_chunk_count(x.size, 1024)
+    assert np.array_equal(c.index[:k].cpu().numpy().astype(np.uint64), oindex.astype(np.uint64))
+    out, err = qlc.decompress(c)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and np.array_equal(out.cpu().numpy(), x)
+
+
 def test_deterministic_repeat():
     x = to_dev(datagen.gaussian(1 << 20, 9).numpy())
     t = gpu_table(x, 0)
