@@ -16,9 +16,11 @@
  *     allocated afterwards.
  *   - qlc_server_submit queues a request (any thread).  A request reserves
  *     its outputs in the pool when admitted: compress = table + total/err +
- *     chunk index + bitstream (n + 16 bytes when the server builds the
+ *     chunk index + bitstream (n + 16 bytes when the server searches the
  *     table, whose cost never exceeds 8 bits per symbol; the 11-bit bound
- *     for a caller's table); decompress = the n output bytes + err.  A
+ *     for a caller's table and for the fixed PAPER_T1 / PAPER_T2 widths,
+ *     which spend up to 9.6 bits per symbol); decompress = the n output
+ *     bytes + err.  A
  *     request whose reservation exceeds the whole budget is rejected at
  *     submit with QLC_ERR_CAPACITY.
  *   - A server thread admits queued requests in arrival order while they

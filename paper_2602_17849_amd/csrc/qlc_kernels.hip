@@ -424,7 +424,7 @@ struct EncSmem {
   __attribute__((aligned(16))) uint32_t words[2][kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
   uint64_t red[kEncThreads / 64];
   uint32_t wave_sum[kEncThreads / 64];
-  uint32_t seg, epoch, cap_hit, bad_table;
+  uint32_t seg, epoch, cap_hit, bad_table, is_last;
 };
 
 // Encoder LUT entry of a table's (len << 11) | code word: code | len << 16.
@@ -791,14 +791,22 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   // ---- last workgroup to finish publishes the error and resets the state ----
   if (tid == 0) {
     if (S.cap_hit) set_error(&hdr->enc_err, QLC_ERR_CAPACITY);
-    const uint32_t done = atomic_add_u32(&hdr->enc_done, 1u);
-    if (done == nseg - 1) {
-      *err_out = load_relaxed_u32(&hdr->enc_err);
-      store_relaxed_u32(&hdr->enc_err, 0);
-      store_relaxed_u32(&hdr->enc_ticket, 0);
-      store_relaxed_u32(&hdr->enc_done, 0);
-      store_relaxed_u32(&hdr->enc_epoch, (epoch + 1) & kEpochMask);
-    }
+    S.is_last = atomic_add_u32(&hdr->enc_done, 1u) == nseg - 1;
+  }
+  __syncthreads();
+  if (!S.is_last) return;
+  // Every workgroup has finished reading its predecessors' words, so the
+  // words this launch published are cleared: a later launch never sees a
+  // word tagged by an earlier one, however far the 22-bit epoch has wrapped
+  // (words of other sizes' layouts never carry bit 63: those bytes hold
+  // segment counts below 2^21 or bit counts below 2^40).
+  for (uint32_t k = tid; k < nseg; k += kEncThreads) store_relaxed_u64(&seg_word[k], 0);
+  if (tid == 0) {
+    *err_out = load_relaxed_u32(&hdr->enc_err);
+    store_relaxed_u32(&hdr->enc_err, 0);
+    store_relaxed_u32(&hdr->enc_ticket, 0);
+    store_relaxed_u32(&hdr->enc_done, 0);
+    store_relaxed_u32(&hdr->enc_epoch, (epoch + 1) & kEpochMask);
   }
 }
 

@@ -143,10 +143,21 @@ struct qlc_server {
   uint64_t chunks(uint64_t n) const {
     return (n + cfg.chunk_symbols - 1) / cfg.chunk_symbols;
   }
+  // Bitstream bytes reserved for a compress request.  A table the server
+  // searches from the request's own histogram never costs more than 8 bits
+  // per symbol (every search mode has an all-equal-length candidate of 8
+  // bits), so n + 16 bytes hold its stream; a caller's table, or the fixed
+  // widths of Table 1 or Table 2 (9.59 bits per symbol on uniform bytes),
+  // get the 11-bit bound.
+  uint64_t bits_capacity(const qlc_request& r) const {
+    const bool searched = cfg.layout_mode != QLC_LAYOUT_PAPER_T1 &&
+                          cfg.layout_mode != QLC_LAYOUT_PAPER_T2;
+    return (r.table || !searched) ? qlc_encode_bound_bytes(r.n) : round_up(r.n + 16, 16);
+  }
   // Pool bytes a request holds from admission to release.
   uint64_t reservation(const qlc_request& r) const {
     if (r.kind == QLC_REQUEST_DECOMPRESS) return round_up(r.n ? r.n : 1) + kAlign;
-    const uint64_t cap = r.table ? qlc_encode_bound_bytes(r.n) : round_up(r.n + 16, 16);
+    const uint64_t cap = bits_capacity(r);
     const uint64_t idx = 8 * (chunks(r.n) ? chunks(r.n) : 1);
     return (r.table ? 0 : round_up(sizeof(qlc_table))) + kAlign + round_up(idx) + round_up(cap);
   }
@@ -182,7 +193,7 @@ struct qlc_server {
     j.chunk_index = reinterpret_cast<uint64_t*>(b);
     b += round_up(8 * (chunks(r.n) ? chunks(r.n) : 1));
     j.bits = b;
-    j.bits_capacity = r.table ? qlc_encode_bound_bytes(r.n) : round_up(r.n + 16, 16);
+    j.bits_capacity = bits_capacity(r);
   }
 
   // Admit queued requests into a free slot (arrival order, within budget).
