@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qlc_oracle.c")
+_SRC_MT = os.path.join(_HERE, "qlc_oracle_mt.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle_qlc.so")
 
 MODE_SEARCH_QUAD = 0
@@ -53,14 +54,15 @@ class _Table(ctypes.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C, -O2, no vectorisation tricks)."""
+    """Compile the oracle with gcc (plain C, -O2, no vectorisation tricks;
+    OpenMP for the multi-threaded variants)."""
+    srcs = [_SRC, _SRC_MT, os.path.join(_HERE, "qlc_oracle.h")]
     if force or not os.path.exists(_LIB_PATH) or (
-        os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
-                                          os.path.getmtime(os.path.join(_HERE, "qlc_oracle.h")))):
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(p) for p in srcs)):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-             _SRC, "-o", tmp])
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-fopenmp",
+             _SRC, _SRC_MT, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -106,6 +108,16 @@ def lib():
         L.qref_decode.argtypes = [u8p, ctypes.c_uint64, u64p, ctypes.c_uint32, tp,
                                   ctypes.c_uint64, u8p]
         L.qref_decode.restype = ctypes.c_int
+        L.qref_histogram_mt.argtypes = [u8p, ctypes.c_uint64, u64p, ctypes.c_int]
+        L.qref_histogram_mt.restype = None
+        L.qref_encode_mt.argtypes = [u8p, ctypes.c_uint64, tp, ctypes.c_uint32, u8p,
+                                     ctypes.c_uint64, u64p, u64p, ctypes.c_int]
+        L.qref_encode_mt.restype = ctypes.c_int
+        L.qref_decode_mt.argtypes = [u8p, ctypes.c_uint64, u64p, ctypes.c_uint32, tp,
+                                     ctypes.c_uint64, u8p, ctypes.c_int]
+        L.qref_decode_mt.restype = ctypes.c_int
+        L.qref_mt_threads.argtypes = [ctypes.c_int]
+        L.qref_mt_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -279,4 +291,58 @@ def decode(bits: np.ndarray, total_bits: int, index: np.ndarray, chunk_symbols: 
     st = lib().qref_decode(_ptr(b, ctypes.c_uint8), total_bits, _ptr(idx, ctypes.c_uint64),
                            chunk_symbols, ctypes.byref(table._raw), n,
                            _ptr(out, ctypes.c_uint8))
+    return int(st), out[:n]
+
+
+# ------------------------------------------------------------------ threads
+def mt_threads(threads: int = 0) -> int:
+    """Threads the multi-threaded oracle runs with (0: OpenMP's default,
+    i.e. every host core unless OMP_NUM_THREADS says otherwise)."""
+    return int(lib().qref_mt_threads(threads))
+
+
+def histogram_mt(x: np.ndarray, threads: int = 0) -> np.ndarray:
+    """histogram() over contiguous slices in parallel (same counts)."""
+    x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
+    h = np.zeros(256, dtype=np.uint64)
+    lib().qref_histogram_mt(_ptr(x, ctypes.c_uint8), x.size, _ptr(h, ctypes.c_uint64), threads)
+    return h
+
+
+def encode_mt(x: np.ndarray, table: Table, chunk_symbols: int = 4096, cap_bytes=None,
+              threads: int = 0):
+    """encode() over ranges of whole chunks in parallel (same bytes)."""
+    x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
+    n = x.size
+    total = encoded_bits(x, table) if cap_bytes is None else 0
+    nbytes = 4 * ((total + 31) // 32)
+    if cap_bytes is None:
+        cap_bytes = nbytes
+    bits = np.empty(max(cap_bytes, 1), dtype=np.uint8)
+    index = np.zeros(max(chunk_count(n, chunk_symbols), 1), dtype=np.uint64)
+    tb = np.zeros(1, dtype=np.uint64)
+    st = lib().qref_encode_mt(_ptr(x, ctypes.c_uint8), n, ctypes.byref(table._raw),
+                              chunk_symbols, _ptr(bits, ctypes.c_uint8), cap_bytes,
+                              _ptr(index, ctypes.c_uint64), _ptr(tb, ctypes.c_uint64), threads)
+    nbytes = 4 * ((int(tb[0]) + 31) // 32)
+    return (int(st), bits[:nbytes] if st == OK else bits[:0],
+            index[:chunk_count(n, chunk_symbols)], int(tb[0]))
+
+
+def decode_mt(bits: np.ndarray, total_bits: int, index: np.ndarray, chunk_symbols: int,
+              table: Table, n: int, threads: int = 0):
+    """decode() over ranges of whole chunks in parallel (same status and,
+    on success, the same bytes)."""
+    b = np.ascontiguousarray(bits, dtype=np.uint8).reshape(-1)
+    if total_bits > 8 * b.size:
+        raise ValueError("bitstream buffer shorter than total_bits")
+    if b.size == 0:
+        b = np.zeros(4, dtype=np.uint8)
+    idx = np.ascontiguousarray(index, dtype=np.uint64).reshape(-1)
+    if idx.size == 0:
+        idx = np.zeros(1, dtype=np.uint64)
+    out = np.zeros(max(n, 1), dtype=np.uint8)
+    st = lib().qref_decode_mt(_ptr(b, ctypes.c_uint8), total_bits, _ptr(idx, ctypes.c_uint64),
+                              chunk_symbols, ctypes.byref(table._raw), n,
+                              _ptr(out, ctypes.c_uint8), threads)
     return int(st), out[:n]

@@ -245,6 +245,21 @@ uint64_t qref_encoded_bits(const uint8_t* x, uint64_t n, const qref_table* t) {
   return total;
 }
 
+uint64_t qref_encode_range(const uint8_t* x, uint64_t i0, uint64_t i1,
+                           const qref_table* t, uint32_t chunk_symbols,
+                           uint64_t bit0, uint8_t* bits_out,
+                           uint64_t* index_out) {
+  uint64_t k = bit0;
+  for (uint64_t i = i0; i < i1; ++i) {
+    if (i % chunk_symbols == 0) index_out[i / chunk_symbols] = k;
+    uint32_t code = t->code[x[i]];
+    uint32_t len = t->len[x[i]];
+    for (uint32_t j = 0; j < len; ++j) /* most significant bit first */
+      put_bit(bits_out, k++, (code >> (len - 1 - j)) & 1u);
+  }
+  return k;
+}
+
 int qref_encode(const uint8_t* x, uint64_t n, const qref_table* t,
                 uint32_t chunk_symbols, uint8_t* bits_out, uint64_t cap_bytes,
                 uint64_t* index_out, uint64_t* total_bits_out) {
@@ -254,14 +269,7 @@ int qref_encode(const uint8_t* x, uint64_t n, const qref_table* t,
   if (total_bits_out) *total_bits_out = total;
   if (nbytes > cap_bytes) return QREF_ERR_CAPACITY;
   memset(bits_out, 0, (size_t)nbytes);
-  uint64_t k = 0;
-  for (uint64_t i = 0; i < n; ++i) {
-    if (i % chunk_symbols == 0) index_out[i / chunk_symbols] = k;
-    uint32_t code = t->code[x[i]];
-    uint32_t len = t->len[x[i]];
-    for (uint32_t j = 0; j < len; ++j) /* most significant bit first */
-      put_bit(bits_out, k++, (code >> (len - 1 - j)) & 1u);
-  }
+  qref_encode_range(x, 0, n, t, chunk_symbols, 0, bits_out, index_out);
   return QREF_OK;
 }
 
@@ -282,12 +290,12 @@ static int read_bits(const uint8_t* bits, uint64_t total, uint64_t* pos,
   return 1;
 }
 
-int qref_decode(const uint8_t* bits, uint64_t total_bits,
-                const uint64_t* index, uint32_t chunk_symbols,
-                const qref_table* t, uint64_t n, uint8_t* out) {
-  if (chunk_symbols == 0) return QREF_ERR_INVALID_ARGUMENT;
+int qref_decode_range(const uint8_t* bits, uint64_t total_bits,
+                      const uint64_t* index, uint32_t chunk_symbols,
+                      const qref_table* t, uint64_t n, uint8_t* out,
+                      uint64_t j0, uint64_t j1) {
   uint64_t nchunks = (n + chunk_symbols - 1) / chunk_symbols;
-  for (uint64_t j = 0; j < nchunks; ++j) {
+  for (uint64_t j = j0; j < j1; ++j) {
     uint64_t pos = index[j];
     uint64_t end = (j + 1 < nchunks) ? index[j + 1] : total_bits;
     if (j == 0 && pos != 0) return QREF_ERR_CORRUPT_STREAM;
@@ -307,6 +315,17 @@ int qref_decode(const uint8_t* bits, uint64_t total_bits,
     }
     if (pos != end) return QREF_ERR_CORRUPT_STREAM;
   }
+  return QREF_OK;
+}
+
+int qref_decode(const uint8_t* bits, uint64_t total_bits,
+                const uint64_t* index, uint32_t chunk_symbols,
+                const qref_table* t, uint64_t n, uint8_t* out) {
+  if (chunk_symbols == 0) return QREF_ERR_INVALID_ARGUMENT;
+  uint64_t nchunks = (n + chunk_symbols - 1) / chunk_symbols;
+  int st = qref_decode_range(bits, total_bits, index, chunk_symbols, t, n, out,
+                             0, nchunks);
+  if (st != QREF_OK) return st;
   if (nchunks == 0 && total_bits != 0) return QREF_ERR_CORRUPT_STREAM;
   return QREF_OK;
 }

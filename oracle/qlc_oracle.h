@@ -129,6 +129,35 @@ int qref_decode(const uint8_t* bits, uint64_t total_bits,
                 const uint64_t* index, uint32_t chunk_symbols,
                 const qref_table* t, uint64_t n, uint8_t* out);
 
+/* Building blocks of the encode / decode above, over a sub-range (used by
+ * the multi-threaded variants below; no arithmetic of their own).
+ * qref_encode_range writes the codes of x[i0, i1) from stream bit bit0 on
+ * into a zeroed buffer and the index entries of the chunk starts inside
+ * the range; returns the bit after the last code.  qref_decode_range
+ * decodes chunks [j0, j1) of a stream (status as qref_decode). */
+uint64_t qref_encode_range(const uint8_t* x, uint64_t i0, uint64_t i1,
+                           const qref_table* t, uint32_t chunk_symbols,
+                           uint64_t bit0, uint8_t* bits_out,
+                           uint64_t* index_out);
+int qref_decode_range(const uint8_t* bits, uint64_t total_bits,
+                      const uint64_t* index, uint32_t chunk_symbols,
+                      const qref_table* t, uint64_t n, uint8_t* out,
+                      uint64_t j0, uint64_t j1);
+
+/* Multi-threaded oracle (OpenMP, qlc_oracle_mt.c): the same results as the
+ * single-threaded functions, byte for byte, computed over contiguous
+ * slices (histogram) or ranges of whole chunks (encode, decode) by
+ * `threads` threads (<= 0: OpenMP's default). */
+void qref_histogram_mt(const uint8_t* x, uint64_t n, uint64_t* h, int threads);
+int qref_encode_mt(const uint8_t* x, uint64_t n, const qref_table* t,
+                   uint32_t chunk_symbols, uint8_t* bits_out, uint64_t cap_bytes,
+                   uint64_t* index_out, uint64_t* total_bits_out, int threads);
+int qref_decode_mt(const uint8_t* bits, uint64_t total_bits,
+                   const uint64_t* index, uint32_t chunk_symbols,
+                   const qref_table* t, uint64_t n, uint8_t* out, int threads);
+/* Threads an OpenMP parallel region with `threads` (<= 0: default) runs. */
+int qref_mt_threads(int threads);
+
 #ifdef __cplusplus
 }
 #endif
