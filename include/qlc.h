@@ -193,6 +193,30 @@ qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
                         uint32_t* err_out, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* qlc_compress for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments and results as qlc_compress without a workspace.
+ * Instead of `ws`, the call uses a workspace of
+ * QLC_COMPRESS_NOALLOC_SCRATCH_BYTES held in a device array inside the
+ * library (one per device, kept until the process ends; looked up and
+ * zeroed by the first call on each device, on that call's stream).  No
+ * hipMalloc, hipFree or allocating library routine is called.
+ *   - n <= QLC_COMPRESS_NOALLOC_MAX_SYMBOLS (2^30), else
+ *     QLC_ERR_INVALID_ARGUMENT and nothing is launched; every other
+ *     argument rule and error is that of qlc_compress.
+ *   - Every call on one device shares that device's array: calls whose
+ *     work overlaps on the device (different streams, or host threads
+ *     without ordering between them) race and give undefined results.
+ *     Calls in stream order are safe; each leaves the array ready for the
+ *     next. */
+#define QLC_COMPRESS_NOALLOC_MAX_SYMBOLS (1ull << 30)
+#define QLC_COMPRESS_NOALLOC_SCRATCH_BYTES 1074688u
+qlc_status qlc_compress_noalloc(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
+                                qlc_table* table_out, uint32_t chunk_symbols,
+                                uint8_t* bits_out, uint64_t bits_capacity_bytes,
+                                uint64_t* chunk_index_out, uint64_t* total_bits_out,
+                                uint32_t* err_out, hipStream_t stream);
+
 /* Step 6 (Implementation section, decoding): decode n symbols of the stream
  * `bits` (4*ceil(*total_bits/32) readable bytes) into out.  Each chunk is
  * decoded independently from its index entry.  *err_out =

@@ -122,6 +122,44 @@ uint32_t persistent_grid(bool decode, uint32_t requested) {
   return g ? g : 1;
 }
 
+// ---- the allocation-free compress: a file-scope device workspace ----------
+// Sized for the largest single-tensor workspace up to kStaticMaxSymbols
+// symbols (at most 1025 segments: header, per-XCD histograms, 1025 segment
+// histograms and bit-count words).  Each device the library runs on holds
+// its own copy until the process ends.
+constexpr uint64_t kStaticMaxSymbols = 1ull << 30;
+constexpr size_t kStaticWsBytes =
+    (kWsSegOffset + 1025 * (256 * sizeof(uint32_t) + sizeof(uint64_t)) + 255) & ~size_t(255);
+static_assert(kStaticWsBytes == QLC_COMPRESS_NOALLOC_SCRATCH_BYTES, "scratch size in qlc.h");
+
+static __device__ __align__(256) uint8_t scratch[kStaticWsBytes];
+
+// Device address of `scratch` on each device, looked up (and the array
+// zeroed, on the caller's stream) by the first call on that device.  The
+// array's name is a host-side stand-in: only these addresses reach kernels.
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+std::once_flag g_scratch_once[kMaxDevices];
+
+hipError_t static_workspace(hipStream_t stream, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::call_once(g_scratch_once[dev], [dev, stream] {
+    void* p = nullptr;
+    hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    // a fill kernel rather than a memset node, so that a first call under
+    // graph capture records a plain kernel
+    if (r == hipSuccess) r = launch_zero(p, kStaticWsBytes, stream);
+    g_scratch_ptr[dev] = r == hipSuccess ? p : nullptr;
+    g_scratch_err[dev] = r;
+  });
+  if (g_scratch_err[dev] != hipSuccess) return g_scratch_err[dev];
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 }  // namespace qlc
 
@@ -257,6 +295,18 @@ qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode, qlc
                                   reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
                                   chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
                                   stream));
+}
+
+qlc_status qlc_compress_noalloc(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
+                                qlc_table* table_out, uint32_t chunk_symbols, uint8_t* bits_out,
+                                uint64_t bits_capacity_bytes, uint64_t* chunk_index_out,
+                                uint64_t* total_bits_out, uint32_t* err_out,
+                                hipStream_t stream) {
+  if (n > kStaticMaxSymbols) return QLC_ERR_INVALID_ARGUMENT;
+  void* ws = nullptr;
+  if (static_workspace(stream, &ws) != hipSuccess) return QLC_ERR_HIP;
+  return qlc_compress(in, n, mode, table_out, chunk_symbols, bits_out, bits_capacity_bytes,
+                      chunk_index_out, total_bits_out, err_out, ws, kStaticWsBytes, stream);
 }
 
 qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits, const uint64_t* chunk_index,

@@ -119,6 +119,8 @@ _SIGNATURES = {
     "qlc_encode": ([_vp, _u64, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_compress": ([_vp, _u64, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp],
                      ctypes.c_int),
+    "qlc_compress_noalloc": ([_vp, _u64, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp],
+                             ctypes.c_int),
     "qlc_decode": ([_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_batched_workspace_bytes": ([_u32, _u64, _u32, _vp], _sz),
     "qlc_encode_batched": ([_vp, _u32, ctypes.c_int, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -251,6 +253,21 @@ def qlc_compress(x: torch.Tensor, mode: int, table_out: torch.Tensor, chunk_symb
     _check(lib().qlc_compress(_p(x), n, mode, _p(table_out), chunk_symbols, _p(bits_out),
                               _nbytes(bits_out), _p(index_out), _p(total_out), _p(err_out), _p(ws),
                               _nbytes(ws), _stream(stream)), "qlc_compress")
+
+
+COMPRESS_NOALLOC_MAX_SYMBOLS = 1 << 30
+
+
+def qlc_compress_noalloc(x: torch.Tensor, mode: int, table_out: torch.Tensor,
+                         chunk_symbols: int, bits_out: torch.Tensor, index_out: torch.Tensor,
+                         total_out: torch.Tensor, err_out: torch.Tensor, stream=None,
+                         n: int | None = None):
+    """qlc_compress without a workspace argument (the library's own device
+    array serves as workspace; calls overlapping on one device race)."""
+    n = x.numel() if n is None else n
+    _check(lib().qlc_compress_noalloc(_p(x), n, mode, _p(table_out), chunk_symbols, _p(bits_out),
+                                      _nbytes(bits_out), _p(index_out), _p(total_out),
+                                      _p(err_out), _stream(stream)), "qlc_compress_noalloc")
 
 
 def qlc_decode(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor, chunk_symbols: int,
