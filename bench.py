@@ -45,47 +45,103 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str):
-    """HBM traffic per launch measured by rocprofv3 counters (profiles/),
-    valid only while the kernel sources are unchanged."""
+def load_profile(kernel: str) -> dict:
+    """rocprofv3 figures of one kernel from profiles/traffic.json: HBM bytes
+    per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) and the average
+    kernel-trace duration, valid only while the kernel sources are
+    unchanged (empty otherwise)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if rec.get("source_hash") != kernel_source_hash():
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+        return {}
+    return rec.get("kernels", {}).get(kernel) or {}
 
 
-def cpu_baseline(x_host, chunk, budget_s=12.0):
-    """The CPU oracle (single-threaded C) on a bounded prefix sample of the
-    same tensor: histogram + table + encode + decode, repeated for about
-    `budget_s` seconds of host time."""
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(x_host, chunk, reps=5, st_sample=1 << 25):
+    """The CPU oracle as it stands, timed on this host: the OpenMP oracle on
+    every host core over the whole workload tensor, and the single-threaded
+    oracle on one core over the tensor's first `st_sample` symbols (its
+    full-tensor run would take about a minute per repetition).  Each op is
+    timed on its own (build_table = histogram + rank + layout search + LUTs;
+    encode; decode), median of `reps` after one warm-up; the multi-threaded
+    outputs are checked against the single-threaded ones on the sample."""
     import numpy as np
 
     import oracle
     oracle.build()
-    n_sample = 1 << 24  # 16 Mi symbols, the first 1/16 of the tensor
-    xs = np.ascontiguousarray(x_host[:n_sample])
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        h = oracle.histogram(xs)
-        t = oracle.build_table(h, oracle.MODE_SEARCH_QUAD)
-        st, bits, index, total = oracle.encode(xs, t, chunk)
-        st2, out = oracle.decode(bits, total, index, chunk, t, xs.size)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or reps >= 100:
-            break
-    assert st == 0 and st2 == 0 and np.array_equal(out, xs)
-    rate = reps * xs.size / el / 1e9
-    return {"value": round(rate, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d symbols of the workload tensor, %d repetition(s) of "
-                      "histogram+table+encode+decode, %.1f s" % (xs.size, reps, el)}
+    threads = oracle.mt_threads(0)
+
+    def median_time(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    def ops(x, mt, table=None):
+        if mt:
+            hist = lambda: oracle.histogram_mt(x, threads)
+            enc = lambda t: oracle.encode_mt(x, t, chunk, threads=threads)
+            dec = lambda e, t: oracle.decode_mt(e[1], e[3], e[2], chunk, t, x.size, threads)
+        else:
+            hist = lambda: oracle.histogram(x)
+            enc = lambda t: oracle.encode(x, t, chunk)
+            dec = lambda e, t: oracle.decode(e[1], e[3], e[2], chunk, t, x.size)
+        t_bt = median_time(lambda: oracle.build_table(hist(), oracle.MODE_SEARCH_QUAD))
+        if table is None:
+            table = oracle.build_table(hist(), oracle.MODE_SEARCH_QUAD)
+        e = enc(table)
+        t_enc = median_time(lambda: enc(table))
+        d = dec(e, table)
+        t_dec = median_time(lambda: dec(e, table))
+        assert e[0] == 0 and d[0] == 0 and np.array_equal(d[1], x), "oracle round trip"
+        n = x.size
+        res = {"threads": threads if mt else 1, "symbols": int(n),
+               "build_table_gbps": round(n / t_bt / 1e9, 4),
+               "encode_gbps": round(n / t_enc / 1e9, 4),
+               "decode_gbps": round(n / t_dec / 1e9, 4),
+               "step_gbps": round(n / (t_bt + t_enc + t_dec) / 1e9, 4),
+               "build_table_s": round(t_bt, 4), "encode_s": round(t_enc, 4),
+               "decode_s": round(t_dec, 4)}
+        return res, e, table
+
+    mt, e_mt, table = ops(np.ascontiguousarray(x_host), True)
+    print("cpu baseline, multi-threaded: %s" % mt, file=sys.stderr, flush=True)
+    # the single-threaded encode and decode of the sample use the whole
+    # tensor's table, so that its stream is the prefix of the whole stream
+    xs = np.ascontiguousarray(x_host[:st_sample])
+    st, e_st, _ = ops(xs, False, table)
+    print("cpu baseline, single-threaded: %s" % st, file=sys.stderr, flush=True)
+    # the multi-threaded stream starts with the single-threaded stream of
+    # the prefix sample (whole bytes; the index entries of its chunks)
+    nb = e_st[3] // 8
+    k = (xs.size + chunk - 1) // chunk
+    assert np.array_equal(e_mt[1][:nb], e_st[1][:nb]) and np.array_equal(e_mt[2][:k], e_st[2])
+    return {"value": mt["step_gbps"], "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "multi-threaded oracle (OpenMP, %d threads) on the whole %d-symbol "
+                      "workload tensor: build_table + encode + decode, each the median of %d "
+                      "runs after a warm-up; single-threaded oracle on 1 core over the first "
+                      "%d symbols (encode and decode with the whole tensor's table)"
+                      % (threads, x_host.size, reps, xs.size),
+                      "multi_threaded": mt, "single_threaded": st,
+                      "host_cpu": _host_cpu(), "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
 BATCH_WORKLOAD = ("1152 shards (18 x 64), sizes log-uniform in 1-32 MiB, multiples of 32 B "
@@ -196,6 +252,154 @@ def run_batched(dev, steps, plain_steps=2, fixed=None):
     }
 
 
+SMALL_WORKLOAD = ("single 1 Mi-symbol e4m3 tensor 1024x1024: FP32 N(0,1), block-32 "
+                  "power-of-two scale, RNE e4m3; per-tensor SEARCH_QUAD table; seed 0")
+
+
+def run_small(dev, reps=200):
+    """Latency of one compress call and one decode call on the 1 Mi-symbol
+    tensor (launch-bound: the data moves in well under a microsecond at
+    HBM rates), eager launches timed one by one with HIP events, median."""
+    import numpy as np
+    import torch
+
+    from paper_2602_17849_amd import datagen, qlc
+
+    x = datagen.single_tensor_gaussian(seed=0, device=dev)
+    n = x.numel()
+    stream = torch.cuda.current_stream()
+    out = {"workload": SMALL_WORKLOAD, "symbols": n, "timing": "median of %d calls, HIP "
+           "events around each call on the launch stream" % reps}
+    for C in (256, 2048):
+        ws = qlc.new_workspace(n, C, dev)
+        table = qlc.new_table(dev)
+        bits = torch.empty(qlc.qlc_encode_bound_bytes(n), dtype=torch.uint8, device=dev)
+        index = torch.empty(qlc.qlc_chunk_count(n, C), dtype=torch.int64, device=dev)
+        total = torch.empty(1, dtype=torch.int64, device=dev)
+        err = torch.zeros(1, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        derr = torch.zeros(1, dtype=torch.int32, device=dev)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        for k in range(reps + 5):
+            e = ev[k - 5] if k >= 5 else None
+            if e:
+                e[0].record(stream)
+            qlc.qlc_compress(x, qlc.LAYOUT_SEARCH_QUAD, table, C, bits, index, total, err, ws)
+            if e:
+                e[1].record(stream)
+            qlc.qlc_decode(bits, total, index, C, table, n, y, derr, ws)
+            if e:
+                e[2].record(stream)
+        torch.cuda.synchronize()
+        assert int(err.item()) == 0 and int(derr.item()) == 0 and torch.equal(x, y)
+        tc = float(np.median([e[0].elapsed_time(e[1]) for e in ev])) * 1e3
+        td = float(np.median([e[1].elapsed_time(e[2]) for e in ev])) * 1e3
+        out["C%d" % C] = {"compress_us": round(tc, 2), "decode_us": round(td, 2),
+                          "compress_gbps": round(n / tc / 1e3, 2),
+                          "decode_gbps": round(n / td / 1e3, 2),
+                          "bits_per_symbol": round(int(total.item()) / n, 5)}
+    return out
+
+
+def run_calibrated(dev, x, C, reps=10):
+    """Encode and decode of the workload tensor with a table fixed in
+    advance: built on the device from a calibration tensor of the same
+    recipe (seed 101), standing in for a per-tensor-type table obtained a
+    priori.  No histogram pass over the workload tensor itself."""
+    import torch
+
+    from paper_2602_17849_amd import datagen, qlc
+
+    n = x.numel()
+    calib = datagen.single_tensor_laplace(seed=101, device=dev)
+    table = qlc.new_table(dev)
+    ws = qlc.new_workspace(n, C, dev)
+    qlc.qlc_build_table(calib, qlc.LAYOUT_SEARCH_QUAD, table, ws)
+    del calib
+    bits = torch.empty(qlc.qlc_encode_bound_bytes(n), dtype=torch.uint8, device=dev)
+    index = torch.empty(qlc.qlc_chunk_count(n, C), dtype=torch.int64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    y = torch.empty_like(x)
+    derr = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for k in range(reps + 2):
+        e = ev[k - 2] if k >= 2 else None
+        if e:
+            e[0].record(stream)
+        qlc.qlc_encode(x, table, C, bits, index, total, err, ws)
+        if e:
+            e[1].record(stream)
+        qlc.qlc_decode(bits, total, index, C, table, n, y, derr, ws)
+        if e:
+            e[2].record(stream)
+    torch.cuda.synchronize()
+    assert int(err.item()) == 0 and int(derr.item()) == 0 and torch.equal(x, y)
+    te = sum(e[0].elapsed_time(e[1]) for e in ev) / reps / 1e3
+    td = sum(e[1].elapsed_time(e[2]) for e in ev) / reps / 1e3
+    tb = int(total.item())
+    enc_bytes = n + 4 * ((tb + 31) // 32) + 8 * qlc.qlc_chunk_count(n, C)
+    return {"table": "SEARCH_QUAD table built from a calibration tensor of the same recipe "
+                     "(seed 101), fixed before the workload tensor is seen",
+            "bits_per_symbol": round(tb / n, 5),
+            "encode_gbps": round(n / te / 1e9, 2), "decode_gbps": round(n / td / 1e9, 2),
+            "encode_hbm_frac": round(enc_bytes / te / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+STRESS_WORKLOAD = ("three 4,294,967,296-byte buffers in one batched call, C = 4096: "
+                   "(i) uniform random bytes (seed 4), (ii) N(0,1) block-32 e4m3 with 90% of "
+                   "the bytes 0x00 (seed 5), (iii) OCP-style e4m3, N(0,1) block-32 with the "
+                   "448 scale rule, 0x7F/0xFF never emitted (seed 6)")
+
+
+def run_stress(dev, reps=3):
+    """The three 4 GiB buffers through the batched form (one encode launch
+    and one decode launch for all three jobs), under SEARCH_QUAD and under
+    Table 1's fixed widths, with the expansion of each buffer."""
+    import torch
+
+    from paper_2602_17849_amd import datagen, qlc
+
+    N, C = 1 << 32, 4096
+    kinds = ("uniform", "zeros90", "ocp_gaussian")
+    b = qlc.Batch([N] * 3, chunk_symbols=C, device=dev, capacity="bound")
+    for i, k in enumerate(kinds):
+        b.input(i).copy_(datagen.stress_buffer(k, N, device=dev))
+    torch.cuda.synchronize()
+    print("stress: 3 x 4 GiB generated", file=sys.stderr, flush=True)
+    ws = b.workspace()
+    stream = torch.cuda.current_stream()
+    res = {"workload": STRESS_WORKLOAD, "symbols": 3 * N, "chunk_symbols": C}
+    for name, mode in (("SEARCH_QUAD", qlc.LAYOUT_SEARCH_QUAD), ("PAPER_T1", qlc.LAYOUT_PAPER_T1)):
+        b.encode(ws, mode)
+        b.decode(ws)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        for e in ev:
+            e[0].record(stream)
+            b.encode(ws, mode)
+            e[1].record(stream)
+            b.decode(ws)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        assert not b.err.any().item(), "stress batch reported an error"
+        assert torch.equal(b.out, b.inp), "stress round trip"
+        te = sum(e[0].elapsed_time(e[1]) for e in ev) / reps / 1e3
+        td = sum(e[1].elapsed_time(e[2]) for e in ev) / reps / 1e3
+        tot = [int(v) for v in b.total.tolist()]
+        res[name] = {
+            "encode_gbps": round(3 * N / te / 1e9, 2), "decode_gbps": round(3 * N / td / 1e9, 2),
+            "bits_per_symbol": {k: round(t / N, 5) for k, t in zip(kinds, tot)},
+            "expansion_pct": {k: round(100.0 * (t / (8.0 * N) - 1.0), 3)
+                              for k, t in zip(kinds, tot)}}
+    res["note"] = ("expansion = code bits / input bits - 1; the chunk index adds 8 bytes per "
+                   "%d symbols (%.3f%%) and the table 264 bytes" % (C, 100.0 * 8 / C))
+    del b, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 SERVE_WORKLOAD = ("Poisson arrivals, mean 2000 req/s for 10 s (seed 3), 50/50 compress / "
                   "decompress, sizes log-uniform 64 KiB-64 MiB (multiples of 32 B) of Laplace "
                   "block-32 e4m3; compress inputs are slices of a resident 1 GiB tensor, "
@@ -288,6 +492,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 1 Mi-symbol latency, calibrated-table and 4 GiB legs")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--batched-tuning", default="",
                     help="C,LOG2_SEGMENT,LAG for the batched form instead of the autotuner")
@@ -297,7 +503,6 @@ def main():
               "(each tensor shard is compressed independently on its own GPU)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2602_17849_amd import datagen, qlc
@@ -316,6 +521,8 @@ def main():
     err = torch.zeros(1, dtype=torch.int32, device=dev)
     out = torch.empty(n, dtype=torch.uint8, device=dev)
     derr = torch.zeros(1, dtype=torch.int32, device=dev)
+    # written before every step: evicts the tensor from the 256 MB Infinity Cache
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
@@ -328,7 +535,8 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
+        flush.fill_(k & 0xFF)
         step()
     torch.cuda.synchronize()
     assert int(err.item()) == 0 and int(derr.item()) == 0
@@ -338,13 +546,16 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        flush.fill_(k & 0xFF)
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert int(err.item()) == 0 and int(derr.item()) == 0
+    assert torch.equal(out, x), "round trip mismatch"
     t_comp = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
     t_dec = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
     ms_per_step = wall / args.steps * 1e3
+    del flush
 
     # per-kernel rates: encode with the table fixed, histogram+table alone
     def timed(fn, reps=10):
@@ -374,6 +585,7 @@ def main():
         torch.cuda.synchronize()
         layouts[name] = round(qlc.parse_table(lt)["cost_bits"] / n, 5)
     t_tab = timed(lambda: qlc.qlc_build_table(x, qlc.LAYOUT_SEARCH_QUAD, table, ws))
+    qlc.qlc_compress(x, qlc.LAYOUT_SEARCH_QUAD, table, C, bits, index, total, err, ws)
     torch.cuda.synchronize()
     tb = int(total.item())
     L = tb / n
@@ -382,7 +594,18 @@ def main():
     # algorithmic bytes of one decode launch: read stream + index, write symbols
     dec_bytes = stream_bytes + index_bytes + n
     achieved = dec_bytes / t_dec / 1e9
-    traffic = load_traffic("k_decode")
+    prof = load_profile("k_decode")
+    roof = {"kernel": "k_decode", "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": prof.get("bytes_per_launch"),
+            "algorithmic_bytes_per_launch": dec_bytes,
+            "timing": "HIP events around the decode launch in each timed step (launch gap "
+                      "included)"}
+    if prof.get("avg_us"):
+        a = dec_bytes / (prof["avg_us"] * 1e-6) / 1e9
+        roof["rocprof_avg_us"] = round(prof["avg_us"], 2)
+        roof["rocprof_achieved"] = round(a, 1)
+        roof["rocprof_frac"] = round(a / HBM_PEAK_GBS, 4)
 
     res = {
         "metric": METRIC,
@@ -399,6 +622,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "symbols": n, "chunk_symbols": C,
                    "layout_mode": "SEARCH_QUAD"},
+        "cache": "a 512 MiB device write before every step (outside the event-timed region, "
+                 "inside ms_per_step) evicts the input from the 256 MB Infinity Cache; within "
+                 "a step each kernel finds what the kernel before it left there",
         "compress_gbps": round(n / t_comp / 1e9, 2),
         "decode_gbps": round(n / t_dec / 1e9, 2),
         "encode_fixed_table_gbps": round(n / t_enc / 1e9, 2),
@@ -408,22 +634,28 @@ def main():
         "compressibility_with_index_and_table": round(
             1 - (stream_bytes + index_bytes + 264) / n, 5),
         "bits_per_symbol_by_layout": layouts,
-        "roofline": {"kernel": "k_decode", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dec_bytes},
+        "roofline": roof,
     }
     x_host = None if args.no_cpu_baseline else x.cpu().numpy()
-    if not args.no_batched:
-        del x, out, bits, ws
+    if not args.no_extra:
+        res["calibrated_table"] = run_calibrated(dev, x, C)
+        print("calibrated_table: %s" % res["calibrated_table"], file=sys.stderr, flush=True)
+    del x, out, bits, ws
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        res["small_tensor"] = run_small(dev)
+        print("small_tensor: %s" % res["small_tensor"], file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
+    if not args.no_batched:
         fixed = tuple(int(v) for v in args.batched_tuning.split(",")) if args.batched_tuning else None
         res["batched"] = run_batched(dev, max(3, min(args.steps, 10)), fixed=fixed)
         torch.cuda.empty_cache()
     if not args.no_serving:
         res["serving"] = run_serving(dev, args.serve_seconds)
         torch.cuda.empty_cache()
+    if not args.no_extra:
+        res["stress_4gib"] = run_stress(dev)
+        print("stress_4gib: %s" % res["stress_4gib"], file=sys.stderr, flush=True)
     if x_host is not None:
         res["cpu_baseline"] = cpu_baseline(x_host, C)
     print(json.dumps(res), flush=True)

@@ -85,7 +85,7 @@ def kernel_stats(d):
 def collect(chunk):
     os.makedirs(OUT, exist_ok=True)
     bench = ["python3", "bench.py", "--steps", "5", "--warmup", "2", "--no-cpu-baseline",
-             "--no-batched", "--no-serving", "--chunk", str(chunk)]
+             "--no-batched", "--no-serving", "--no-extra", "--chunk", str(chunk)]
     cmds = {}
     cmds["trace"] = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv",
                      "-d", os.path.join(OUT, "trace"), "-o", "trace", "--"] + bench
@@ -124,6 +124,12 @@ def collect(chunk):
         kernels[s] = {"fetch_kb": fetch_kb, "write_kb": write_kb, "read_bytes": rd,
                       "write_bytes": wr,
                       "bytes_per_launch": (rd + wr) if rd is not None and wr is not None else None}
+    stats = kernel_stats(os.path.join(OUT, "trace"))
+    for r in stats:
+        nm = short(r.get("Name", ""))
+        if nm in kernels:
+            kernels[nm]["avg_us"] = float(r["AverageNs"]) / 1e3
+            kernels[nm]["calls"] = int(r["Calls"])
     rec = {"source_hash": kernel_source_hash(), "chunk_symbols": chunk,
            "copy_bytes": COPY_BYTES, "copy_fetch_kb": f_read, "copy_write_kb": f_write,
            "read_scale": scale_r, "write_scale": scale_w, "kernels": kernels,
@@ -132,7 +138,6 @@ def collect(chunk):
     with open(os.path.join(OUT, "traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
 
-    stats = kernel_stats(os.path.join(OUT, "trace"))
     lines = ["# libqlc kernels on the single 256 MiB tensor (8192x32768 Laplace e4m3)", "",
              "Kernel durations: `%s` (run from the repository root)" % " ".join(cmds["trace"]),
              "", "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
@@ -167,7 +172,7 @@ def collect_batched(tuning):
     cmd = ["rocprofv3", "--kernel-trace", "--stats", "--output-format", "csv",
            "-d", os.path.join(OUT, "trace_batched"), "-o", "trace", "--",
            "python3", "bench.py", "--steps", "3", "--warmup", "1", "--no-cpu-baseline",
-           "--no-serving", "--batched-tuning", tuning]
+           "--no-serving", "--no-extra", "--batched-tuning", tuning]
     run(cmd, os.path.join(OUT, "trace_batched.log"))
     stats = kernel_stats(os.path.join(OUT, "trace_batched"))
     c, l2, lag = tuning.split(",")
@@ -204,7 +209,7 @@ def collect_sq(chunk, kernel="k_decode"):
     four cycles)."""
     os.makedirs(OUT, exist_ok=True)
     bench = ["python3", "bench.py", "--steps", "3", "--warmup", "1", "--no-cpu-baseline",
-             "--no-batched", "--no-serving", "--chunk", str(chunk)]
+             "--no-batched", "--no-serving", "--no-extra", "--chunk", str(chunk)]
     vals, cmds = {}, []
     for i, ctrs in enumerate(SQ_PASSES):
         d = os.path.join(OUT, "sq%d" % (i + 1))
