@@ -101,7 +101,19 @@ typedef enum qlc_layout_mode {
    * knob the Conclusion section leaves open): cheapest non-decreasing
    * 4-tuple of widths, greedy fill, codes of 2 + width bits.  The table's
    * areas 4..7 get width 0xFF, no ranks. */
-  QLC_LAYOUT_SEARCH_AREAS4 = 32
+  QLC_LAYOUT_SEARCH_AREAS4 = 32,
+  /* Small alphabets (the eXmY family's 4- and 6-bit types, Experimental
+   * Setup; areas and symbols per area are the knobs the Conclusion leaves
+   * open): the cheapest non-decreasing width tuple, greedy fill, for 16
+   * symbols (4-bit codes such as e2m1) in 2 areas (1-bit area code, codes
+   * of 1..5 bits) or 4 areas (2-bit area code, 2..6 bits), and for 64
+   * symbols (6-bit codes such as e3m2) in 4 areas (2..8 bits) or 8 areas
+   * (3-bit area code, 3..9 bits).  An area whose width is the symbol width
+   * stores the raw rank.  Used with the *_sym entry points below. */
+  QLC_LAYOUT_M16_AREAS2 = 48,
+  QLC_LAYOUT_M16_AREAS4 = 49,
+  QLC_LAYOUT_M64_AREAS4 = 50,
+  QLC_LAYOUT_M64_AREAS8 = 51
 } qlc_layout_mode;
 #define QLC_LAYOUT_SEARCH_DISTINCT(k) ((qlc_layout_mode)(16 + (k)))
 
@@ -229,6 +241,50 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits,
                       uint32_t* err_out, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* ---- Small alphabets: 4-bit and 6-bit symbols, packed ----
+ *
+ * The *_sym entry points take `symbol_bits` = 4, 6 or 8 and otherwise the
+ * arguments of the byte entry points above (which are the symbol_bits = 8
+ * case).  n counts symbols; a buffer of n symbols holds
+ * ceil(n * symbol_bits / 8) bytes:
+ *   - 4 bits: two symbols per byte, symbol 2k in the low nibble of byte k
+ *     (the usual packing of e2m1 pairs);
+ *   - 6 bits: symbol i in bits 6i .. 6i + 5 of the buffer read as a
+ *     little-endian bit string (bit b of byte k is string bit 8k + b), four
+ *     symbols per three bytes.
+ * Decoded buffers follow the same packing; pad bits of the last byte are
+ * written as zeros.  Layout modes must be for the same alphabet
+ * (QLC_LAYOUT_M16_* for 4 bits, QLC_LAYOUT_M64_* for 6 bits, the others
+ * for 8 bits), else QLC_ERR_INVALID_ARGUMENT before any launch; an encode
+ * or decode given a table built for another alphabet reports
+ * QLC_ERR_INVALID_ARGUMENT in *err_out and writes nothing.  The stream,
+ * chunk index and table formats are those of the byte codec: a table of M
+ * symbols uses enc / sym_to_rank entries 0..M-1 and rank_to_sym entries
+ * 0..M-1 (the other entries are 0 / identity), and marks the areas it
+ * does not use with width 0xFF. */
+qlc_status qlc_histogram_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                             uint64_t* hist_out, void* ws, size_t ws_bytes, hipStream_t stream);
+qlc_status qlc_histogram_accumulate_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                                        uint64_t* hist_inout, void* ws, size_t ws_bytes,
+                                        hipStream_t stream);
+qlc_status qlc_build_table_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                               qlc_layout_mode mode, qlc_table* table_out, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+qlc_status qlc_compress_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                            qlc_layout_mode mode, qlc_table* table_out, uint32_t chunk_symbols,
+                            uint8_t* bits_out, uint64_t bits_capacity_bytes,
+                            uint64_t* chunk_index_out, uint64_t* total_bits_out,
+                            uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream);
+qlc_status qlc_encode_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                          const qlc_table* table, uint32_t chunk_symbols, uint8_t* bits_out,
+                          uint64_t bits_capacity_bytes, uint64_t* chunk_index_out,
+                          uint64_t* total_bits_out, uint32_t* err_out, void* ws, size_t ws_bytes,
+                          hipStream_t stream);
+qlc_status qlc_decode_sym(const uint8_t* bits, const uint64_t* total_bits,
+                          const uint64_t* chunk_index, uint32_t chunk_symbols,
+                          const qlc_table* table, uint64_t n, uint32_t symbol_bits, uint8_t* out,
+                          uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- Batched form: many tensors (shards) of uneven sizes per launch ----
  *
  * The same steps as qlc_compress / qlc_decode applied to every job of a
@@ -294,7 +350,19 @@ qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs,
                               const qlc_batch_tuning* h_tuning, void* ws,
                               size_t ws_bytes, hipStream_t stream);
 
-/* Host-side persisted table form: width[8] followed by rank_to_sym[256]. */
+/* The batched calls for jobs of `symbol_bits`-bit symbols (4, 6 or 8; all
+ * jobs of one call share it; packing and mode rules as the *_sym entry
+ * points above). */
+qlc_status qlc_encode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t symbol_bits,
+                                  qlc_layout_mode mode, uint32_t chunk_symbols,
+                                  const qlc_batch_tuning* h_tuning, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+qlc_status qlc_decode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t symbol_bits,
+                                  uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning,
+                                  void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Host-side persisted table form: width[8] followed by rank_to_sym[256]
+ * (tables of the byte alphabet). */
 qlc_status qlc_table_serialize(const qlc_table* h_table,
                                uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]);
 /* Rebuild a full table on the host (8 areas, or 4 areas when widths 4..7

@@ -200,24 +200,40 @@ qlc_status qlc_workspace_init(void* ws, size_t ws_bytes, hipStream_t stream) {
   return hip_status(launch_zero(ws, ws_bytes, stream));
 }
 
-qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out, void* ws,
-                         size_t ws_bytes, hipStream_t stream) {
-  if ((n && !in) || !hist_out || !ws || n >= QLC_MAX_SYMBOLS_PER_CALL) return QLC_ERR_INVALID_ARGUMENT;
+qlc_status qlc_histogram_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                             uint64_t* hist_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if ((n && !in) || !hist_out || !ws || n >= QLC_MAX_SYMBOLS_PER_CALL ||
+      !valid_symbol_bits(symbol_bits))
+    return QLC_ERR_INVALID_ARGUMENT;
   if (!aligned(in, 16) || !aligned(hist_out, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
   if (ws_bytes < ws_bytes_for(n)) return QLC_ERR_INVALID_ARGUMENT;
   WsView v = carve(ws, n);
-  return hip_status(launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, hist_out, kHistGlobal,
-                                     0, nullptr, stream));
+  return hip_status(launch_histogram(in, n, symbol_bits, v.hdr, v.xcd_part, v.seg_hist, hist_out,
+                                     kHistGlobal, 0, nullptr, stream));
+}
+
+qlc_status qlc_histogram(const uint8_t* in, uint64_t n, uint64_t* hist_out, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  return qlc_histogram_sym(in, n, 8, hist_out, ws, ws_bytes, stream);
+}
+
+qlc_status qlc_histogram_accumulate_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                                        uint64_t* hist_inout, void* ws, size_t ws_bytes,
+                                        hipStream_t stream) {
+  if ((n && !in) || !hist_inout || !ws || n >= QLC_MAX_SYMBOLS_PER_CALL ||
+      !valid_symbol_bits(symbol_bits))
+    return QLC_ERR_INVALID_ARGUMENT;
+  if (!aligned(in, 16) || !aligned(hist_inout, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
+  if (ws_bytes < ws_bytes_for(n)) return QLC_ERR_INVALID_ARGUMENT;
+  WsView v = carve(ws, n);
+  return hip_status(launch_histogram(in, n, symbol_bits, v.hdr, v.xcd_part, v.seg_hist,
+                                     hist_inout, kHistGlobal | kHistAccumulate, 0, nullptr,
+                                     stream));
 }
 
 qlc_status qlc_histogram_accumulate(const uint8_t* in, uint64_t n, uint64_t* hist_inout, void* ws,
                                     size_t ws_bytes, hipStream_t stream) {
-  if ((n && !in) || !hist_inout || !ws || n >= QLC_MAX_SYMBOLS_PER_CALL) return QLC_ERR_INVALID_ARGUMENT;
-  if (!aligned(in, 16) || !aligned(hist_inout, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
-  if (ws_bytes < ws_bytes_for(n)) return QLC_ERR_INVALID_ARGUMENT;
-  WsView v = carve(ws, n);
-  return hip_status(launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, hist_inout,
-                                     kHistGlobal | kHistAccumulate, 0, nullptr, stream));
+  return qlc_histogram_accumulate_sym(in, n, 8, hist_inout, ws, ws_bytes, stream);
 }
 
 qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
@@ -227,17 +243,30 @@ qlc_status qlc_table_from_histogram(const uint64_t* hist, qlc_layout_mode mode,
   return hip_status(launch_table_from_hist(hist, (uint32_t)mode, table_out, stream));
 }
 
-qlc_status qlc_build_table(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
-                           qlc_table* table_out, void* ws, size_t ws_bytes, hipStream_t stream) {
-  if ((n && !in) || !table_out || !ws || !valid_layout_mode((uint32_t)mode) ||
+namespace {
+// a layout mode for symbols of `symbol_bits` bits
+bool mode_for(qlc_layout_mode mode, uint32_t symbol_bits) {
+  return valid_layout_mode((uint32_t)mode) && mode_symbol_bits((uint32_t)mode) == symbol_bits;
+}
+}  // namespace
+
+qlc_status qlc_build_table_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                               qlc_layout_mode mode, qlc_table* table_out, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  if ((n && !in) || !table_out || !ws || !mode_for(mode, symbol_bits) ||
       n >= QLC_MAX_SYMBOLS_PER_CALL)
     return QLC_ERR_INVALID_ARGUMENT;
   if (!aligned(in, 16) || !aligned(table_out, 16) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
   if (ws_bytes < ws_bytes_for(n)) return QLC_ERR_INVALID_ARGUMENT;
   WsView v = carve(ws, n);
-  return hip_status(launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, nullptr,
+  return hip_status(launch_histogram(in, n, symbol_bits, v.hdr, v.xcd_part, v.seg_hist, nullptr,
                                      kHistGlobal | kHistBuildTable, (uint32_t)mode, table_out,
                                      stream));
+}
+
+qlc_status qlc_build_table(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
+                           qlc_table* table_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return qlc_build_table_sym(in, n, 8, mode, table_out, ws, ws_bytes, stream);
 }
 
 namespace {
@@ -257,11 +286,13 @@ qlc_status check_encode_args(const uint8_t* in, uint64_t n, const void* table, u
 }
 }  // namespace
 
-qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
-                      uint32_t chunk_symbols, uint8_t* bits_out, uint64_t bits_capacity_bytes,
-                      uint64_t* chunk_index_out, uint64_t* total_bits_out, uint32_t* err_out,
-                      void* ws, size_t ws_bytes, hipStream_t stream) {
+qlc_status qlc_encode_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                          const qlc_table* table, uint32_t chunk_symbols, uint8_t* bits_out,
+                          uint64_t bits_capacity_bytes, uint64_t* chunk_index_out,
+                          uint64_t* total_bits_out, uint32_t* err_out, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
   uint32_t log2c = 0;
+  if (!valid_symbol_bits(symbol_bits)) return QLC_ERR_INVALID_ARGUMENT;
   qlc_status st = check_encode_args(in, n, table, chunk_symbols, bits_out, bits_capacity_bytes,
                                     chunk_index_out, total_bits_out, err_out, ws, ws_bytes, &log2c);
   if (st != QLC_OK) return st;
@@ -269,9 +300,38 @@ qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
   // segment bit counts straight from the table's lengths (the segment
   // histograms' region holds them)
   uint64_t* seg_bits = reinterpret_cast<uint64_t*>(v.seg_hist);
-  hipError_t e = launch_segment_bits(in, n, table, seg_bits, stream);
+  hipError_t e = launch_segment_bits(in, n, symbol_bits, table, seg_bits, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode(in, n, table, nullptr, seg_bits, log2c,
+  return hip_status(launch_encode(in, n, symbol_bits, table, nullptr, seg_bits, log2c,
+                                  reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
+                                  chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
+                                  stream));
+}
+
+qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
+                      uint32_t chunk_symbols, uint8_t* bits_out, uint64_t bits_capacity_bytes,
+                      uint64_t* chunk_index_out, uint64_t* total_bits_out, uint32_t* err_out,
+                      void* ws, size_t ws_bytes, hipStream_t stream) {
+  return qlc_encode_sym(in, n, 8, table, chunk_symbols, bits_out, bits_capacity_bytes,
+                        chunk_index_out, total_bits_out, err_out, ws, ws_bytes, stream);
+}
+
+qlc_status qlc_compress_sym(const uint8_t* in, uint64_t n, uint32_t symbol_bits,
+                            qlc_layout_mode mode, qlc_table* table_out, uint32_t chunk_symbols,
+                            uint8_t* bits_out, uint64_t bits_capacity_bytes,
+                            uint64_t* chunk_index_out, uint64_t* total_bits_out,
+                            uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  uint32_t log2c = 0;
+  if (!mode_for(mode, symbol_bits)) return QLC_ERR_INVALID_ARGUMENT;
+  qlc_status st = check_encode_args(in, n, table_out, chunk_symbols, bits_out, bits_capacity_bytes,
+                                    chunk_index_out, total_bits_out, err_out, ws, ws_bytes, &log2c);
+  if (st != QLC_OK) return st;
+  WsView v = carve(ws, n);
+  hipError_t e = launch_histogram(in, n, symbol_bits, v.hdr, v.xcd_part, v.seg_hist, nullptr,
+                                  kHistSegment | kHistGlobal | kHistBuildTable, (uint32_t)mode,
+                                  table_out, stream);
+  if (e != hipSuccess) return QLC_ERR_HIP;
+  return hip_status(launch_encode(in, n, symbol_bits, table_out, v.seg_hist, nullptr, log2c,
                                   reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
                                   chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
                                   stream));
@@ -281,20 +341,8 @@ qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode, qlc
                         uint32_t chunk_symbols, uint8_t* bits_out, uint64_t bits_capacity_bytes,
                         uint64_t* chunk_index_out, uint64_t* total_bits_out, uint32_t* err_out,
                         void* ws, size_t ws_bytes, hipStream_t stream) {
-  uint32_t log2c = 0;
-  if (!valid_layout_mode((uint32_t)mode)) return QLC_ERR_INVALID_ARGUMENT;
-  qlc_status st = check_encode_args(in, n, table_out, chunk_symbols, bits_out, bits_capacity_bytes,
-                                    chunk_index_out, total_bits_out, err_out, ws, ws_bytes, &log2c);
-  if (st != QLC_OK) return st;
-  WsView v = carve(ws, n);
-  hipError_t e = launch_histogram(in, n, v.hdr, v.xcd_part, v.seg_hist, nullptr,
-                                  kHistSegment | kHistGlobal | kHistBuildTable, (uint32_t)mode,
-                                  table_out, stream);
-  if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode(in, n, table_out, v.seg_hist, nullptr, log2c,
-                                  reinterpret_cast<uint32_t*>(bits_out), bits_capacity_bytes / 4,
-                                  chunk_index_out, total_bits_out, err_out, v.hdr, v.seg_word,
-                                  stream));
+  return qlc_compress_sym(in, n, 8, mode, table_out, chunk_symbols, bits_out, bits_capacity_bytes,
+                          chunk_index_out, total_bits_out, err_out, ws, ws_bytes, stream);
 }
 
 qlc_status qlc_compress_noalloc(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
@@ -309,11 +357,13 @@ qlc_status qlc_compress_noalloc(const uint8_t* in, uint64_t n, qlc_layout_mode m
                       chunk_index_out, total_bits_out, err_out, ws, kStaticWsBytes, stream);
 }
 
-qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits, const uint64_t* chunk_index,
-                      uint32_t chunk_symbols, const qlc_table* table, uint64_t n, uint8_t* out,
-                      uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+qlc_status qlc_decode_sym(const uint8_t* bits, const uint64_t* total_bits,
+                          const uint64_t* chunk_index, uint32_t chunk_symbols,
+                          const qlc_table* table, uint64_t n, uint32_t symbol_bits, uint8_t* out,
+                          uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream) {
   uint32_t log2c = 0;
-  if (!valid_chunk(chunk_symbols, &log2c) || n >= QLC_MAX_SYMBOLS_PER_CALL)
+  if (!valid_chunk(chunk_symbols, &log2c) || n >= QLC_MAX_SYMBOLS_PER_CALL ||
+      !valid_symbol_bits(symbol_bits))
     return QLC_ERR_INVALID_ARGUMENT;
   if (!total_bits || !table || !err_out || !ws || (n && (!bits || !chunk_index || !out)))
     return QLC_ERR_INVALID_ARGUMENT;
@@ -322,8 +372,15 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits, const uin
     return QLC_ERR_INVALID_ARGUMENT;
   if (ws_bytes < ws_bytes_for(0)) return QLC_ERR_INVALID_ARGUMENT;
   WsView v = carve(ws, 0);
-  return hip_status(launch_decode(bits, total_bits, chunk_index, log2c, table, n, out, err_out,
-                                  v.hdr, stream));
+  return hip_status(launch_decode(bits, total_bits, chunk_index, log2c, table, n, symbol_bits, out,
+                                  err_out, v.hdr, stream));
+}
+
+qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits, const uint64_t* chunk_index,
+                      uint32_t chunk_symbols, const qlc_table* table, uint64_t n, uint8_t* out,
+                      uint32_t* err_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return qlc_decode_sym(bits, total_bits, chunk_index, chunk_symbols, table, n, 8, out, err_out,
+                        ws, ws_bytes, stream);
 }
 
 size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint32_t chunk_symbols,
@@ -337,11 +394,12 @@ size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint
   return round256(batch_units_offset(n_jobs) + (enc > dec ? enc : dec));
 }
 
-qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_mode mode,
-                              uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning, void* ws,
-                              size_t ws_bytes, hipStream_t stream) {
+qlc_status qlc_encode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t symbol_bits,
+                                  qlc_layout_mode mode, uint32_t chunk_symbols,
+                                  const qlc_batch_tuning* h_tuning, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
   uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
-  if (!valid_chunk(chunk_symbols, &log2c) || !valid_layout_mode((uint32_t)mode) ||
+  if (!valid_chunk(chunk_symbols, &log2c) || !mode_for(mode, symbol_bits) ||
       !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return QLC_ERR_INVALID_ARGUMENT;
   if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
@@ -351,16 +409,24 @@ qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_m
   hipError_t e = launch_batch_plan(jobs, n_jobs, false, log2_seg, v.max_units, lag, v.hdr, v.js,
                                    v.job_hist, v.unit_job, v.seg_word, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode_batched(jobs, (uint32_t)mode, log2_seg, log2c, v.hdr, v.js,
-                                          v.job_hist, v.unit_job, v.seg_word, v.seg_hist,
-                                          persistent_grid(false, wgs), stream));
+  return hip_status(launch_encode_batched(jobs, symbol_bits, (uint32_t)mode, log2_seg, log2c,
+                                          v.hdr, v.js, v.job_hist, v.unit_job, v.seg_word,
+                                          v.seg_hist, persistent_grid(false, wgs), stream));
 }
 
-qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chunk_symbols,
-                              const qlc_batch_tuning* h_tuning, void* ws, size_t ws_bytes,
-                              hipStream_t stream) {
+qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_mode mode,
+                              uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  return qlc_encode_batched_sym(jobs, n_jobs, 8, mode, chunk_symbols, h_tuning, ws, ws_bytes,
+                                stream);
+}
+
+qlc_status qlc_decode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t symbol_bits,
+                                  uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning,
+                                  void* ws, size_t ws_bytes, hipStream_t stream) {
   uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
-  if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
+  if (!valid_chunk(chunk_symbols, &log2c) || !valid_symbol_bits(symbol_bits) ||
+      !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return QLC_ERR_INVALID_ARGUMENT;
   if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
   if (n_jobs == 0) return QLC_OK;
@@ -369,8 +435,14 @@ qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chu
   hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + kDecThreadsLog2, v.max_units, 0, v.hdr, v.js,
                                    v.job_hist, v.unit_job, nullptr, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_decode_batched(jobs, log2c, v.hdr, v.js, v.unit_job,
+  return hip_status(launch_decode_batched(jobs, symbol_bits, log2c, v.hdr, v.js, v.unit_job,
                                           persistent_grid(true, wgs), stream));
+}
+
+qlc_status qlc_decode_batched(const qlc_job* jobs, uint32_t n_jobs, uint32_t chunk_symbols,
+                              const qlc_batch_tuning* h_tuning, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  return qlc_decode_batched_sym(jobs, n_jobs, 8, chunk_symbols, h_tuning, ws, ws_bytes, stream);
 }
 
 qlc_status qlc_table_serialize(const qlc_table* h_table, uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]) {

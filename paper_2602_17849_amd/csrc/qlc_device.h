@@ -112,6 +112,48 @@ constexpr CandidateTable4 make_candidate_table4() {
   return t;
 }
 
+// Candidates of the small-alphabet layouts: M symbols (16 or 64), A areas
+// (2, 4 or 8), non-decreasing A-tuples over 0..log2(M) whose greedy fill
+// leaves every area non-empty and covers the M ranks, in lexicographic
+// order (the index is the tie-break); widths in nibbles 0..A-1 (the others
+// 0xF), `ends` holds the end rank of areas 0..A-2.
+template <int kMax>
+struct SmallCandidateTable {
+  Candidate c[kMax];
+  int count;
+};
+
+template <int kM, int kA, int kMax>
+constexpr SmallCandidateTable<kMax> make_small_candidates() {
+  SmallCandidateTable<kMax> t{};
+  int maxw = 0;
+  while ((1 << maxw) < kM) ++maxw;
+  int w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int n = 0;
+  while (true) {
+    uint32_t head = 0;
+    for (int a = 0; a < kA - 1; ++a) head += 1u << w[a];
+    if (head < (uint32_t)kM && head + (1u << w[kA - 1]) >= (uint32_t)kM) {
+      uint32_t pk = 0xFFFFFFFFu, f = 0;
+      uint64_t ends = 0;
+      for (int a = 0; a < kA; ++a) {
+        pk = (pk & ~(0xFu << (4 * a))) | (uint32_t(w[a]) << (4 * a));
+        f += 1u << w[a];
+        if (a < kA - 1) ends |= uint64_t(f) << (8 * a);
+      }
+      if (n < kMax) t.c[n] = Candidate{pk, uint32_t(n), ends};
+      ++n;
+    }
+    int pos = kA - 1;
+    while (pos >= 0 && w[pos] == maxw) --pos;
+    if (pos < 0) break;
+    ++w[pos];
+    for (int a = pos + 1; a < kA; ++a) w[a] = w[pos];
+  }
+  t.count = n;
+  return t;
+}
+
 // Widths of the two printed schemes (Table 1 and Table 2, "#Symbol bits").
 constexpr uint32_t kPaperT1Packed = 0x85433333u;  // 3,3,3,3,3,4,5,8
 constexpr uint32_t kPaperT2Packed = 0x85533331u;  // 1,3,3,3,3,5,5,8

@@ -25,11 +25,24 @@ constexpr int kDecThreadsLog2 = QLC_DEC_THREADS_LOG2;
 constexpr int kDecThreads = 1 << kDecThreadsLog2;  // decode workgroup: one lane per chunk
 constexpr int kStageGroups = QLC_DEC_STAGE_GROUPS;  // decoded groups staged per lane (8 or 16)
 static_assert(kStageGroups == 8 || kStageGroups == 16, "stage depth");
-constexpr int kNumXcd = 8;
-// Layout modes: 0..3, SEARCH_DISTINCT_k = 16 + k for k = 1..8, SEARCH_AREAS4 = 32.
+constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies
+// Layout modes: 0..3, SEARCH_DISTINCT_k = 16 + k for k = 1..8, SEARCH_AREAS4 = 32,
+// and the small alphabets 48..51 (16 or 64 symbols).
 inline bool valid_layout_mode(uint32_t m) {
-  return m <= 3u || (m >= 17u && m <= 24u) || m == 32u;
-}            // MI355X: 8 accelerator complex dies
+  return m <= 3u || (m >= 17u && m <= 24u) || m == 32u || (m >= 48u && m <= 51u);
+}
+// Bits per symbol of the alphabet a layout mode codes: 4 (16 symbols),
+// 6 (64 symbols) or 8 (256 symbols).
+__host__ __device__ inline uint32_t mode_symbol_bits(uint32_t m) {
+  return (m == 48u || m == 49u) ? 4u : (m == 50u || m == 51u) ? 6u : 8u;
+}
+// Areas of a layout mode (the area code has log2 of that many bits).
+__host__ __device__ inline uint32_t mode_areas(uint32_t m) {
+  return m == 48u ? 2u : (m == 32u || m == 49u || m == 50u) ? 4u : 8u;
+}
+inline bool valid_symbol_bits(uint32_t b) { return b == 4u || b == 6u || b == 8u; }
+// Bytes holding n symbols of `bits` bits each, packed.
+inline uint64_t packed_bytes(uint64_t n, uint32_t bits) { return (n * bits + 7) / 8; }
 
 // ---- histogram kernel outputs ----------------------------------------------
 constexpr uint32_t kHistSegment = 1;     // write each segment's histogram

@@ -32,11 +32,108 @@ __device__ __forceinline__ void gstore_u2(QLC_GLOBAL uint8_t* p, uint2 v) {
   *(QLC_GLOBAL GVec2*)p = w;
 }
 
+// ---------------------------------------------------------------------------
+// Symbol access by alphabet: 8-bit symbols are bytes; 4-bit symbols are
+// packed two per byte (symbol 2k in the low nibble of byte k); 6-bit
+// symbols four per three bytes (symbol i in bits 6i .. 6i + 5 of the
+// buffer read as a little-endian bit string).  fetch16 returns the 16
+// symbols starting at symbol i (a multiple of 16), one per byte.
+// ---------------------------------------------------------------------------
+template <int kBits>
+struct Sym;
+
+template <>
+struct Sym<8> {
+  static constexpr uint32_t kM = 256;
+  typedef uint4 Raw;  // the bytes of 16 symbols as loaded
+  __device__ static __forceinline__ Raw load16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return gload_u4((const QLC_GLOBAL GVec4*)in, i >> 4);
+  }
+  __device__ static __forceinline__ uint4 expand(const Raw& r) { return r; }
+  __device__ static __forceinline__ uint4 fetch16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return load16(in, i);
+  }
+  __device__ static __forceinline__ uint32_t at(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return in[i];
+  }
+};
+
+// the eight nibbles of w, in order, one per byte of two words
+__device__ __forceinline__ uint2 nibbles_to_bytes(uint32_t w) {
+  const uint32_t lo = w & 0x0F0F0F0Fu, hi = (w >> 4) & 0x0F0F0F0Fu;
+  return make_uint2(__builtin_amdgcn_perm(hi, lo, 0x05010400u),
+                    __builtin_amdgcn_perm(hi, lo, 0x07030602u));
+}
+
+template <>
+struct Sym<4> {
+  static constexpr uint32_t kM = 16;
+  typedef uint2 Raw;
+  __device__ static __forceinline__ Raw load16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    const GVec2 v = *(const QLC_GLOBAL GVec2*)(in + (i >> 1));
+    return make_uint2(v.x, v.y);
+  }
+  __device__ static __forceinline__ uint4 expand(const Raw& r) {
+    const uint2 a = nibbles_to_bytes(r.x), b = nibbles_to_bytes(r.y);
+    return make_uint4(a.x, a.y, b.x, b.y);
+  }
+  __device__ static __forceinline__ uint4 fetch16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return expand(load16(in, i));
+  }
+  __device__ static __forceinline__ uint32_t at(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return (in[i >> 1] >> ((uint32_t)(i & 1) * 4u)) & 15u;
+  }
+};
+
+// four 6-bit fields of the low 24 bits of x, one per byte
+__device__ __forceinline__ uint32_t sixes_to_bytes(uint32_t x) {
+  return (x & 0x3Fu) | ((x << 2) & 0x3F00u) | ((x << 4) & 0x3F0000u) | ((x << 6) & 0x3F000000u);
+}
+
+template <>
+struct Sym<6> {
+  static constexpr uint32_t kM = 64;
+  typedef uint4 Raw;  // three words used
+  __device__ static __forceinline__ Raw load16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    const QLC_GLOBAL uint32_t* p = (const QLC_GLOBAL uint32_t*)(in + (i >> 2) * 3);
+    return make_uint4(p[0], p[1], p[2], 0u);
+  }
+  __device__ static __forceinline__ uint4 expand(const Raw& r) {
+    return make_uint4(sixes_to_bytes(r.x), sixes_to_bytes(__builtin_amdgcn_alignbit(r.y, r.x, 24)),
+                      sixes_to_bytes(__builtin_amdgcn_alignbit(r.z, r.y, 16)),
+                      sixes_to_bytes(r.z >> 8));
+  }
+  __device__ static __forceinline__ uint4 fetch16(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    return expand(load16(in, i));
+  }
+  __device__ static __forceinline__ uint32_t at(const QLC_GLOBAL uint8_t* in, uint64_t i) {
+    const uint64_t bit = i * 6;
+    const uint32_t sh = (uint32_t)(bit & 7);
+    uint32_t v = (uint32_t)in[bit >> 3] >> sh;
+    if (sh > 2) v |= (uint32_t)in[(bit >> 3) + 1] << (8 - sh);
+    return v & 63u;
+  }
+};
+
 __constant__ CandidateTable g_candidates = make_candidate_table();
 static_assert(make_candidate_table().count == kNumCandidates, "candidate count");
 static_assert(make_candidate_table().quad == kNumQuadCandidates, "quad candidate count");
 __constant__ CandidateTable4 g_candidates4 = make_candidate_table4();
 static_assert(make_candidate_table4().count == kNumCandidates4, "4-area candidate count");
+// small alphabets: 16 symbols in 2 or 4 areas, 64 symbols in 4 or 8 areas
+constexpr int kNumCandM16A2 = 5, kNumCandM16A4 = 25, kNumCandM64A4 = 70, kNumCandM64A8 = 693;
+__constant__ SmallCandidateTable<kNumCandM16A2> g_cand_m16a2 =
+    make_small_candidates<16, 2, kNumCandM16A2>();
+__constant__ SmallCandidateTable<kNumCandM16A4> g_cand_m16a4 =
+    make_small_candidates<16, 4, kNumCandM16A4>();
+__constant__ SmallCandidateTable<kNumCandM64A4> g_cand_m64a4 =
+    make_small_candidates<64, 4, kNumCandM64A4>();
+__constant__ SmallCandidateTable<kNumCandM64A8> g_cand_m64a8 =
+    make_small_candidates<64, 8, kNumCandM64A8>();
+static_assert(make_small_candidates<16, 2, kNumCandM16A2>().count == kNumCandM16A2, "count");
+static_assert(make_small_candidates<16, 4, kNumCandM16A4>().count == kNumCandM16A4, "count");
+static_assert(make_small_candidates<64, 4, kNumCandM64A4>().count == kNumCandM64A4, "count");
+static_assert(make_small_candidates<64, 8, kNumCandM64A8>().count == kNumCandM64A8, "count");
 
 
 // ===========================================================================
@@ -65,12 +162,17 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   qlc_table* out = &S.stage;
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  int big = 0;  // a count of 2^48 or more
+  // the alphabet: M symbols of sbits bits; symbols M..255 take no part
+  // (their counts must be zero) and keep ranks M..255 in symbol order
+  const uint32_t sbits = mode_symbol_bits(mode);
+  const uint32_t M = 1u << sbits;
+  int big = 0;  // a count of 2^48 or more, or a count of a symbol outside the alphabet
   for (int s = tid; s < 256; s += nt) {
-    const uint64_t c = h_in[s];
+    uint64_t c = h_in[s];
+    big |= ((c >> 48) != 0 || ((uint32_t)s >= M && c != 0)) ? 1 : 0;
+    if ((uint32_t)s >= M) c = 0;
     S.h[s] = c;
     S.key[s] = (c << 8) | (uint64_t)(255 - s);
-    big |= (c >> 48) != 0 ? 1 : 0;
   }
   big = __syncthreads_or(big);
 
@@ -120,9 +222,9 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
 
   // Layout: fixed printed widths, or the cheapest candidate (ties to the
   // smallest index = lexicographically smallest tuple).
-  // area code bits: 3 (8 areas), or 2 (4 areas) for the 4-area search
-  const uint32_t pbits = mode == QLC_LAYOUT_SEARCH_AREAS4 ? 2u : 3u;
-  const uint32_t na = 1u << pbits;
+  // area code bits: 3 (8 areas), 2 (4 areas) or 1 (2 areas)
+  const uint32_t na = mode_areas(mode);
+  const uint32_t pbits = na == 8 ? 3u : na == 4 ? 2u : 1u;
   uint32_t packed;
   if (mode == QLC_LAYOUT_PAPER_T1) {
     packed = kPaperT1Packed;
@@ -133,12 +235,28 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     // ends come with the candidate, so the eight prefix-sum reads are
     // independent.
     const uint32_t max_distinct = mode == QLC_LAYOUT_SEARCH_QUAD ? 4u
-                                  : (mode == QLC_LAYOUT_SEARCH_ANY ||
-                                     mode == QLC_LAYOUT_SEARCH_AREAS4) ? 8u
-                                                                       : mode - 16u;
-    const Candidate* ct = na == 4 ? g_candidates4.c : g_candidates.c;
-    const int ncand = na == 4 ? kNumCandidates4
-                      : max_distinct <= 4u ? kNumQuadCandidates : kNumCandidates;
+                                  : (mode >= 17u && mode <= 24u) ? mode - 16u : 8u;
+    const Candidate* ct;
+    int ncand;
+    if (mode == QLC_LAYOUT_M16_AREAS2) {
+      ct = g_cand_m16a2.c;
+      ncand = kNumCandM16A2;
+    } else if (mode == QLC_LAYOUT_M16_AREAS4) {
+      ct = g_cand_m16a4.c;
+      ncand = kNumCandM16A4;
+    } else if (mode == QLC_LAYOUT_M64_AREAS4) {
+      ct = g_cand_m64a4.c;
+      ncand = kNumCandM64A4;
+    } else if (mode == QLC_LAYOUT_M64_AREAS8) {
+      ct = g_cand_m64a8.c;
+      ncand = kNumCandM64A8;
+    } else if (na == 4) {
+      ct = g_candidates4.c;
+      ncand = kNumCandidates4;
+    } else {
+      ct = g_candidates.c;
+      ncand = max_distinct <= 4u ? kNumQuadCandidates : kNumCandidates;
+    }
     const uint64_t pN = S.P[256];
     uint64_t best = ~0ull;
     uint32_t best_pk = 0;
@@ -161,7 +279,7 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
           if ((uint32_t)a >= na) break;
-          const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : 256u;
+          const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : M;
           const uint64_t pe = S.P[e];
           cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
           prev = pe;
@@ -192,26 +310,26 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     packed = S.wave_pk[wb];
   }
 
-  // Greedy fill, offsets (an 8-bit area carries the raw rank), cost; the
-  // areas a 4-area table does not use get width 0xFF and no ranks.  Lane a
-  // of wave 0 fills area a: its first rank is the capacity of the areas
-  // before it, capped at 256.
+  // Greedy fill, offsets (an area whose width is the symbol width carries
+  // the raw rank), cost; the areas a table with fewer than 8 areas does not
+  // use get width 0xFF and no ranks.  Lane a of wave 0 fills area a: its
+  // first rank is the capacity of the areas before it, capped at M.
   if (tid < 64) {
     const uint32_t a = (uint32_t)tid & 7u;
     uint32_t f = 0;
     for (uint32_t k = 0; k < a && k < na; ++k) {
       const uint32_t c = f + (1u << ((packed >> (4 * k)) & 15u));
-      f = c < 256u ? c : 256u;
+      f = c < M ? c : M;
     }
     uint64_t term = 0;
     uint32_t w = 0xFFu, first = 256u, cnt = 0u, off = 0u;
     if (a < na) {
       const uint32_t b = (packed >> (4 * a)) & 15u;
       const uint32_t cap = 1u << b;
-      cnt = cap < 256u - f ? cap : 256u - f;
+      cnt = cap < M - f ? cap : M - f;
       w = b;
       first = f;
-      off = (b == 8) ? 0u : f;
+      off = (b == sbits) ? 0u : f;
       term = (uint64_t)(pbits + b) * (S.P[f + cnt] - S.P[f]);
     }
     // sum of the eight lanes' terms (lanes 8.. repeat lanes 0..7)
@@ -236,7 +354,8 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   // code length 0 and every width 0xFF, which the encoders reject.
   const bool unusable = big != 0 || (S.P[256] >> 48) != 0;
 
-  // Encoder LUT (Table 3), indexed by input symbol.
+  // Encoder LUT (Table 3), indexed by input symbol (no code for symbols
+  // outside the alphabet).
   for (int s = tid; s < 256; s += nt) {
     const uint32_t r = S.rank[s];
     uint32_t a = 0;
@@ -244,7 +363,8 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     for (int k = 1; k < 8; ++k) a = (r >= S.first[k]) ? (uint32_t)k : a;
     const uint32_t b = S.width[a];
     const uint32_t code = (a << b) | (r - S.offset[a]);
-    out->enc[s] = unusable ? (uint16_t)0 : (uint16_t)(((pbits + b) << 11) | code);
+    out->enc[s] = (unusable || (uint32_t)s >= M) ? (uint16_t)0
+                                                 : (uint16_t)(((pbits + b) << 11) | code);
     out->rank_to_sym[s] = (uint8_t)S.r2s[s];
     out->sym_to_rank[s] = (uint8_t)r;
   }
@@ -307,28 +427,31 @@ __device__ __forceinline__ void hist_add_vec(uint32_t* sub, uint4 v, uint32_t co
   hist_add_word(sub, v.w, copy);
 }
 
-// Count bytes [seg0, seg1) of `in` into the 32 LDS copies (zeroed by the
-// caller); seg0 is a multiple of 16.
-__device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uint64_t seg0,
+// Count symbols [seg0, seg1) of `in` into the 32 LDS copies (zeroed by the
+// caller); seg0 is a multiple of 16.  Whole groups of 16 symbols are read
+// as one vector each (16, 8 or 12 bytes by the alphabet).
+template <int kBits>
+__device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in_p, uint64_t seg0,
                                              uint64_t seg1, uint32_t* sub, uint32_t tid) {
+  using SI = Sym<kBits>;
+  const QLC_GLOBAL uint8_t* in = (const QLC_GLOBAL uint8_t*)in_p;
   const uint32_t nt = blockDim.x;
   const uint32_t copy = tid & (kHistCopies - 1);
-  const QLC_GLOBAL GVec4* vin = (const QLC_GLOBAL GVec4*)in;
-  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-byte vectors of the segment
+  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-symbol groups of the segment
   uint64_t i = v0 + tid;
   if (i + 3 * nt < v1) {
-    // the next four vectors are loaded before the current four are counted
-    uint4 a = gload_u4(vin, i), b = gload_u4(vin, i + nt);
-    uint4 c = gload_u4(vin, i + 2 * nt), d = gload_u4(vin, i + 3 * nt);
+    // the next four groups are loaded before the current four are counted
+    uint4 a = SI::fetch16(in, i << 4), b = SI::fetch16(in, (i + nt) << 4);
+    uint4 c = SI::fetch16(in, (i + 2 * nt) << 4), d = SI::fetch16(in, (i + 3 * nt) << 4);
     for (;;) {
       const uint64_t nx = i + 4 * nt;
       const bool more = nx + 3 * nt < v1;
       uint4 na = a, nb = b, nc = c, nd = d;
       if (more) {
-        na = gload_u4(vin, nx);
-        nb = gload_u4(vin, nx + nt);
-        nc = gload_u4(vin, nx + 2 * nt);
-        nd = gload_u4(vin, nx + 3 * nt);
+        na = SI::fetch16(in, nx << 4);
+        nb = SI::fetch16(in, (nx + nt) << 4);
+        nc = SI::fetch16(in, (nx + 2 * nt) << 4);
+        nd = SI::fetch16(in, (nx + 3 * nt) << 4);
       }
       hist_add_vec(sub, a, copy);
       hist_add_vec(sub, b, copy);
@@ -342,9 +465,9 @@ __device__ __forceinline__ void hist_segment(const uint8_t* __restrict__ in, uin
       d = nd;
     }
   }
-  for (; i < v1; i += nt) hist_add_vec(sub, gload_u4(vin, i), copy);
+  for (; i < v1; i += nt) hist_add_vec(sub, SI::fetch16(in, i << 4), copy);
   for (uint64_t j = (v1 << 4) + tid; j < seg1; j += nt)  // ragged tail of the input
-    atomicAdd(&sub[((uint32_t)((const QLC_GLOBAL uint8_t*)in)[j] << 5) | copy], 1u);
+    atomicAdd(&sub[(SI::at(in, j) << 5) | copy], 1u);
 }
 
 // Per-bin total of the 32 copies (thread t < 256 sums bin t).
@@ -355,6 +478,7 @@ __device__ __forceinline__ uint32_t hist_bin_total(const uint32_t* sub, uint32_t
   return s;
 }
 
+template <int kBits>
 __global__ __launch_bounds__(kHistThreads) void k_histogram(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg, WsHeader* __restrict__ hdr,
     uint64_t* __restrict__ xcd_part, uint32_t* __restrict__ seg_hist,
@@ -368,7 +492,7 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
 
   const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
-  hist_segment(in, seg0, seg1, S.sub, tid);
+  hist_segment<kBits>(in, seg0, seg1, S.sub, tid);
   __syncthreads();
 
   if (tid < 256) {
@@ -434,6 +558,14 @@ __device__ __forceinline__ uint32_t enc_entry(uint32_t e) {
   return (e & 0x7FFu) | ((e >> 11) << 16);
 }
 
+// Whether symbol s's encoder entry e ((len << 11) | code) is usable for an
+// alphabet of kBits-bit symbols: symbols of the alphabet need a length in
+// 1..11; the others are never read.
+template <int kBits>
+__device__ __forceinline__ bool enc_entry_ok(uint32_t e, uint32_t s) {
+  return s >= Sym<kBits>::kM || ((e >> 11) >= 1 && (e >> 11) <= QLC_MAX_CODE_BITS);
+}
+
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   v = wave_sum_u64(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -484,6 +616,7 @@ __device__ __forceinline__ uint32_t pair_len(uint32_t e0, uint32_t e1) {
 }
 
 // State of a segment's encode carried from tile to tile.
+template <int kBits>
 struct EncSeg {
   const QLC_GLOBAL uint8_t* in;
   uint64_t seg1;
@@ -495,7 +628,7 @@ struct EncSeg {
   bool last_seg;
   __amdgpu_buffer_rsrc_t out_rsrc;   // stream words from seg_w0 on, clipped at cap_words
   QLC_GLOBAL uint64_t* index_out;
-  uint4 nx0, nx1;                    // the next full tile's input (prefetched)
+  typename Sym<kBits>::Raw nx0, nx1;  // the next full tile's input (prefetched, as loaded)
   uint32_t buf;                      // word buffer of the current tile
 };
 
@@ -506,21 +639,23 @@ struct EncSeg {
 // run in the stream, and one block scan of the packed pair of run lengths
 // (b0 | b1 << 16) places both (run bits <= 176, block totals < 2^16).
 // Returns true in a thread one of whose stores would have passed cap_words.
-template <bool kFull>
-__device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, uint32_t tid) {
+template <int kBits, bool kFull>
+__device__ __forceinline__ bool encode_tile(EncSeg<kBits>& E, uint64_t t0, EncSmem& S,
+                                            uint32_t tid) {
+  using SI = Sym<kBits>;
   const uint32_t lane = tid & 63, wave = tid >> 6;
   bool cap = false;
   uint32_t* const Wd = S.words[E.buf];
   uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (whole tiles)
   uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
   if (kFull) {
-    const uint4 v0 = E.nx0, v1 = E.nx1;
+    const typename SI::Raw r0 = E.nx0, r1 = E.nx1;
     {  // prefetch the next tile (this one again when no whole tile follows)
       const uint64_t nt = (t0 + 2 * kEncTile <= E.seg1) ? t0 + kEncTile : t0;
-      const QLC_GLOBAL GVec4* p = (const QLC_GLOBAL GVec4*)(E.in + nt + (uint64_t)tid * 16);
-      E.nx0 = gload_u4(p, 0);
-      E.nx1 = gload_u4(p, kEncThreads);
+      E.nx0 = SI::load16(E.in, nt + (uint64_t)tid * 16);
+      E.nx1 = SI::load16(E.in, nt + kEncTile / 2 + (uint64_t)tid * 16);
     }
+    const uint4 v0 = SI::expand(r0), v1 = SI::expand(r1);
     const uint32_t sw[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -536,7 +671,7 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
 #pragma unroll 1
     for (int k = 0; k < 32; ++k) {
       const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-      const uint32_t l = i < E.seg1 ? (S.lut[E.in[i]] >> 16) : 0u;
+      const uint32_t l = i < E.seg1 ? (S.lut[SI::at(E.in, i)] >> 16) : 0u;
       if (k < 16) b0 += l;
       else b1 += l;
     }
@@ -571,7 +706,7 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
         const uint64_t i =
             t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
         if (i < E.seg1) {
-          const uint32_t e = S.lut[E.in[i]];
+          const uint32_t e = S.lut[SI::at(E.in, i)];
           if (k < 16) P0.put(Wd, e & 0xFFFFu, e >> 16);
           else P1.put(Wd, e & 0xFFFFu, e >> 16);
         }
@@ -630,30 +765,33 @@ __device__ __forceinline__ bool encode_tile(EncSeg& E, uint64_t t0, EncSmem& S, 
 // alternate between the two buffers, so a tile's stores and the next
 // tile's packing need no barrier between them.  Every
 // whole stream word of the segment is stored; its partial first word also
-// carries the previous segment's last bits (recomputed from the 16 symbols
-// before seg0); its partial last word is left to the next segment, unless
+// carries the previous segment's last bits (recomputed from the 32 symbols
+// before seg0, which hold at least 32 bits since every code has at least
+// one); its partial last word is left to the next segment, unless
 // `last_seg` (padded and stored).  Returns true in a thread one of whose
 // stores would have passed cap_words (that store is dropped).  Whole tiles
 // run in a loop of their own, the ragged last tile (if any) after it.
+template <int kBits>
 __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, uint64_t seg0, uint64_t seg1,
                                uint64_t G, bool last_seg, uint32_t log2_chunk,
                                uint32_t* __restrict__ bits_out, uint64_t cap_words,
                                uint64_t* __restrict__ index_out, EncSmem& S, uint32_t tid) {
+  using SI = Sym<kBits>;
   bool cap = false;
   // ---- last bits of the previous segment (recomputed from its input) ----
   if (tid == 0) {
     uint32_t w0 = 0;
     if ((G & 31) != 0) {
       uint64_t acc = 0;
-      for (int k = 16; k >= 1; --k) {
-        const uint32_t e = S.lut[in[seg0 - k]];
+      for (int k = 32; k >= 1; --k) {
+        const uint32_t e = S.lut[SI::at((const QLC_GLOBAL uint8_t*)in, seg0 - k)];
         acc = (acc << (e >> 16)) | (e & 0xFFFFu);
       }
       w0 = ((uint32_t)acc) << (32 - (uint32_t)(G & 31));
     }
     S.words[0][0] = w0;
   }
-  EncSeg E;
+  EncSeg<kBits> E;
   E.in = (const QLC_GLOBAL uint8_t*)in;
   E.seg1 = seg1;
   E.R = G;
@@ -671,25 +809,27 @@ __device__ __forceinline__ bool encode_segment(const uint8_t* __restrict__ in, u
       bits_out + (cap_words > E.seg_w0 ? E.seg_w0 : 0), (short)0,
       (int)(uint32_t)(room < 0xFFFFFFF0ull ? room : 0xFFFFFFF0ull), 0x00020000);
   E.buf = 0;
-  E.nx0 = make_uint4(0, 0, 0, 0);
+  E.nx0 = typename SI::Raw{};
   E.nx1 = E.nx0;
   if (seg0 + kEncTile <= seg1) {
-    const QLC_GLOBAL GVec4* p = (const QLC_GLOBAL GVec4*)(E.in + seg0 + (uint64_t)tid * 16);
-    E.nx0 = gload_u4(p, 0);
-    E.nx1 = gload_u4(p, kEncThreads);
+    E.nx0 = SI::load16(E.in, seg0 + (uint64_t)tid * 16);
+    E.nx1 = SI::load16(E.in, seg0 + kEncTile / 2 + (uint64_t)tid * 16);
   }
   uint64_t t0 = seg0;
-  for (; t0 + kEncTile <= seg1; t0 += kEncTile) cap |= encode_tile<true>(E, t0, S, tid);
-  if (t0 < seg1 || seg0 == seg1) cap |= encode_tile<false>(E, t0, S, tid);
+  for (; t0 + kEncTile <= seg1; t0 += kEncTile) cap |= encode_tile<kBits, true>(E, t0, S, tid);
+  if (t0 < seg1 || seg0 == seg1) cap |= encode_tile<kBits, false>(E, t0, S, tid);
   return cap;
 }
 
 // Bit count of every segment under a given table (the pre-pass of an encode
 // with a fixed table): the segment's code lengths summed through an LDS
 // copy of the length column, no atomics.
+template <int kBits>
 __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
-    const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
+    const uint8_t* __restrict__ in_p, uint64_t n, uint32_t log2_seg,
     const qlc_table* __restrict__ table, uint64_t* __restrict__ seg_bits) {
+  using SI = Sym<kBits>;
+  const QLC_GLOBAL uint8_t* in = (const QLC_GLOBAL uint8_t*)in_p;
   __shared__ uint32_t len[256];
   __shared__ uint64_t red[kHistThreads / 64];
   const uint32_t tid = threadIdx.x;
@@ -697,13 +837,13 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
   __syncthreads();
   const uint64_t seg0 = (uint64_t)blockIdx.x << log2_seg;
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
-  const QLC_GLOBAL GVec4* vin = (const QLC_GLOBAL GVec4*)in;
-  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;
+  const uint64_t v0 = seg0 >> 4, v1 = seg1 >> 4;  // whole 16-symbol groups
   uint32_t s = 0;
   uint64_t i = v0 + tid;
   for (; i + 3 * kHistThreads < v1; i += 4 * kHistThreads) {
-    const uint4 a = gload_u4(vin, i), b = gload_u4(vin, i + kHistThreads);
-    const uint4 c = gload_u4(vin, i + 2 * kHistThreads), d = gload_u4(vin, i + 3 * kHistThreads);
+    const uint4 a = SI::fetch16(in, i << 4), b = SI::fetch16(in, (i + kHistThreads) << 4);
+    const uint4 c = SI::fetch16(in, (i + 2 * kHistThreads) << 4);
+    const uint4 d = SI::fetch16(in, (i + 3 * kHistThreads) << 4);
     const uint32_t w[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
                             c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
 #pragma unroll
@@ -712,14 +852,14 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
            len[w[k] >> 24];
   }
   for (; i < v1; i += kHistThreads) {
-    const uint4 a = gload_u4(vin, i);
+    const uint4 a = SI::fetch16(in, i << 4);
     const uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       s += len[w[k] & 0xFFu] + len[(w[k] >> 8) & 0xFFu] + len[(w[k] >> 16) & 0xFFu] +
            len[w[k] >> 24];
   }
-  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += kHistThreads) s += len[in[j]];
+  for (uint64_t j = (v1 << 4) + tid; j < seg1; j += kHistThreads) s += len[SI::at(in, j)];
   const uint64_t t = wave_sum_u64(s);
   if ((tid & 63) == 0) red[tid >> 6] = t;
   __syncthreads();
@@ -731,6 +871,7 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
   }
 }
 
+template <int kBits>
 __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
     const qlc_table* __restrict__ table, const uint32_t* __restrict__ seg_hist,
@@ -750,10 +891,11 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   S.lut[tid] = enc_entry(e_t);
   for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) (&S.words[0][0])[w] = 0;
   __syncthreads();
-  // A table whose code lengths leave 2..11 is rejected: 11 keeps every LDS
-  // index of the packer in bounds without per-symbol clamps, 2 makes the 16
-  // symbols before a segment hold the 31 bits its first word may need.
-  if ((e_t >> 11) < 2 || (e_t >> 11) > QLC_MAX_CODE_BITS) S.bad_table = 1;
+  // A table whose code lengths leave 1..11 for a symbol of the alphabet, or
+  // that codes another alphabet, is rejected: 11 keeps every LDS index of
+  // the packer in bounds without per-symbol clamps.
+  if (!enc_entry_ok<kBits>(e_t, tid) || (tid == 0 && mode_symbol_bits(table->mode) != kBits))
+    S.bad_table = 1;
   const uint32_t seg = S.seg;
   const uint32_t epoch = S.epoch;
   const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
@@ -780,8 +922,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   const uint64_t seg1 = (seg0 + (1ull << log2_seg)) < n ? seg0 + (1ull << log2_seg) : n;
   bool cap = false;
   if (!bad_table) {
-    cap = encode_segment(in, seg0, seg1, G, seg == nseg - 1, log2_chunk, bits_out, cap_words,
-                         index_out, S, tid);
+    cap = encode_segment<kBits>(in, seg0, seg1, G, seg == nseg - 1, log2_chunk, bits_out,
+                                cap_words, index_out, S, tid);
   } else if (tid == 0) {
     set_error(&hdr->enc_err, QLC_ERR_INVALID_ARGUMENT);
   }
@@ -952,6 +1094,41 @@ __device__ __forceinline__ uint2 pack_group(const uint32_t (&e)[8], uint32_t& er
   return r;
 }
 
+// Eight decoded symbols (one per byte of r, in order) in the output format
+// of the alphabet: bytes (8-bit symbols), four bytes of nibbles (symbol 2k
+// in the low nibble of byte k), or six bytes of 6-bit fields in
+// little-endian bit order (low word, then the low 16 bits of the high one).
+__device__ __forceinline__ uint32_t six_pack(uint32_t x) {
+  return (x & 0x3Fu) | ((x >> 2) & 0xFC0u) | ((x >> 4) & 0x3F000u) | ((x >> 6) & 0xFC0000u);
+}
+template <int kBits>
+__device__ __forceinline__ uint2 pack_out(uint2 r) {
+  if (kBits == 8) return r;
+  if (kBits == 4) {
+    const uint32_t t0 = r.x | (r.x >> 4), t1 = r.y | (r.y >> 4);
+    return make_uint2(__builtin_amdgcn_perm(t1, t0, 0x06040200u), 0u);
+  }
+  const uint32_t lo = six_pack(r.x), hi = six_pack(r.y);
+  return make_uint2(lo | (hi << 24), hi >> 8);
+}
+
+// Store one group's kBits output bytes (from pack_out) at byte address p
+// (a multiple of kBits).
+template <int kBits>
+__device__ __forceinline__ void store_group(QLC_GLOBAL uint8_t* p, uint2 v) {
+  if (kBits == 8) {
+    gstore_u2(p, v);
+  } else if (kBits == 4) {
+    *(QLC_GLOBAL uint32_t*)p = v.x;
+  } else if (((uintptr_t)p & 3u) == 0) {  // 6 bytes: word + half, or half + word
+    *(QLC_GLOBAL uint32_t*)p = v.x;
+    *(QLC_GLOBAL uint16_t*)(p + 4) = (uint16_t)v.y;
+  } else {
+    *(QLC_GLOBAL uint16_t*)p = (uint16_t)v.x;
+    *(QLC_GLOBAL uint32_t*)(p + 2) = (v.x >> 16) | (v.y << 16);
+  }
+}
+
 // Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
 __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __restrict__ lut) {
   const uint32_t q = (uint32_t)L.pm1;
@@ -963,16 +1140,16 @@ __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __rest
 // Code -> symbol LUT of `table` into `lut` (2048 32-bit entries, bit 15 =
 // invalid suffix) and the shift table indexed by the window's top three
 // bits (byte i of sh_hi:sh_lo = 32 - prefix bits - width of the area the
-// top bits name).  A table whose areas 4..7 are marked 0xFF has a 2-bit
-// area code: top bits 2a and 2a + 1 both name area a, so the decode chain
-// is the same for both prefix widths.  Any block size; the caller
-// synchronises before using the LUT.
+// top bits name).  A table whose areas 4..7 (or 2..7) are marked 0xFF has a
+// 2-bit (1-bit) area code: top bits 2a and 2a + 1 (4a .. 4a + 3) all name
+// area a, so the decode chain is the same for every prefix width.  Any
+// block size; the caller synchronises before using the LUT.
 __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint32_t* lut,
                               uint32_t& sh_lo, uint32_t& sh_hi) {
   sh_lo = 0;
   sh_hi = 0;
   {
-    const uint32_t p = table->width[4] == 0xFFu ? 2u : 3u;  // area code bits
+    const uint32_t p = table->width[4] != 0xFFu ? 3u : table->width[2] != 0xFFu ? 2u : 1u;
     const uint32_t na = 1u << p;
     uint32_t w[8], lo[8], off[8], first[8], cnt[8];
 #pragma unroll
@@ -1009,6 +1186,7 @@ __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ tabl
 // onwards, one per lane (tid = threadIdx.x); S.lut holds the code -> symbol
 // LUT.  Returns true in a lane whose chunk is corrupt (or whose index
 // entries are inconsistent).
+template <int kBits>
 __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, uint64_t total,
                              const uint64_t* __restrict__ index_p, uint32_t log2_chunk, uint64_t n,
                              uint8_t* __restrict__ out_p, uint64_t grp, uint32_t sh_lo,
@@ -1083,7 +1261,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     uint32_t sba = 0, sbb = 0;
     bool va = false, vb = false;
     uint2* stage = S.stage + tid * kStageGroups;
-    QLC_GLOBAL uint8_t* o = out + (j << log2_chunk);
+    QLC_GLOBAL uint8_t* o = out + (((j << log2_chunk) * kBits) >> 3);
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
 
@@ -1098,7 +1276,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
 #define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
   {                                                                                     \
     const uint32_t gg = (gidx);                                                         \
-    if (gg < my_groups) stage[stage_slot(gg, tid)] = decode_group(L, S.lut);            \
+    if (gg < my_groups) stage[stage_slot(gg, tid)] = pack_out<kBits>(decode_group(L, S.lut)); \
     if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
     VAL = live && gg < my_groups &&                                                     \
           ((uint64_t)fsb << kSbLog2Bits) < (L.pm1 + 1 - rel0) + kLookaheadBits;         \
@@ -1118,10 +1296,15 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       Superblock pc_, pd_;
       uint32_t sbc = 0, sbd = 0;
       bool vc = false, vd = false;
-      constexpr uint32_t R = kStageGroups;      // lanes per output run
-      constexpr uint32_t kRuns = 64 / R;        // runs per store instruction
-      const uint32_t part = lane % R;
-      QLC_GLOBAL uint8_t* obase = out + ((j_wave + lane / R) << log2_chunk) + part * 8u;
+      // bytes: R lanes per output run, one group each; sub-byte symbols: R / 2
+      // lanes per run, two groups (8 or 12 bytes) each
+      constexpr uint32_t R = kStageGroups;              // groups per flush
+      constexpr uint32_t kGpl = kBits == 8 ? 1u : 2u;   // groups per lane per store
+      constexpr uint32_t kLpr = R / kGpl;               // lanes per run
+      constexpr uint32_t kRuns = 64 / kLpr;             // runs per store instruction
+      const uint32_t part = lane % kLpr;
+      QLC_GLOBAL uint8_t* obase =
+          out + ((((j_wave + lane / kLpr) << log2_chunk) * kBits) >> 3) + part * kGpl * kBits;
       // Software pipelined: the next group's window is read right after the
       // current chain (and after the ring write it may depend on), so its
       // LDS latency overlaps the current group's LUT gathers and packing.
@@ -1141,7 +1324,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     SBX = fsb;                                                                          \
     PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
     fsb += VAL ? 1u : 0u;                                                               \
-    stage[stage_slot((GI), tid)] = pack_group(e, L.errbits);                            \
+    stage[stage_slot((GI), tid)] = pack_out<kBits>(pack_group(e, L.errbits));           \
   }
       // One iteration = R groups and their flush, so that the flush sits at
       // a fixed program point: the waits for loads issued before it then
@@ -1157,10 +1340,24 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (uint32_t k = 0; k < R; ++k) {
-          const uint32_t stid = (tid & ~63u) | (lane / R + kRuns * k);
-          const uint2 v = S.stage[stid * R + stage_slot(g0 + part, stid)];
-          gstore_u2(obase + ((uint64_t)(kRuns * k) << log2_chunk) + g0 * 8, v);
+        for (uint32_t k = 0; k < kLpr; ++k) {
+          const uint32_t stid = (tid & ~63u) | (lane / kLpr + kRuns * k);
+          QLC_GLOBAL uint8_t* dst =
+              obase + ((((uint64_t)(kRuns * k) << log2_chunk) * kBits) >> 3) + g0 * kBits;
+          if (kBits == 8) {
+            gstore_u2(dst, S.stage[stid * R + stage_slot(g0 + part, stid)]);
+          } else {
+            const uint2 a = S.stage[stid * R + stage_slot(g0 + 2 * part, stid)];
+            const uint2 b = S.stage[stid * R + stage_slot(g0 + 2 * part + 1, stid)];
+            if (kBits == 4) {
+              gstore_u2(dst, make_uint2(a.x, b.x));
+            } else {  // 12 bytes at a multiple of 12
+              QLC_GLOBAL uint32_t* d32 = (QLC_GLOBAL uint32_t*)dst;
+              d32[0] = a.x;
+              d32[1] = (a.y & 0xFFFFu) | (b.x << 16);
+              d32[2] = (b.x >> 16) | (b.y << 16);
+            }
+          }
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -1188,7 +1385,8 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
           const uint64_t jj = grp * kDecThreads + stid;
           const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
           if (g + part < ngrp)
-            gstore_u2(out + (jj << log2_chunk) + (uint64_t)(g + part) * 8, v);
+            store_group<kBits>(
+                out + ((((jj << log2_chunk) + (uint64_t)(g + part) * 8) * kBits) >> 3), v);
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -1206,16 +1404,22 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       uint32_t A = __builtin_amdgcn_alignbit(w0, w1, ~q);
       uint32_t B = __builtin_amdgcn_alignbit(w1, w2, ~q);
       uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, ~q);
+      uint64_t acc = 0;  // the partial group, packed (sub-byte symbols)
       for (uint32_t k = 0; k < rem; ++k) {
         const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
         const uint32_t s = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
         const uint32_t e = S.lut[A >> s];
         L.errbits |= e;
-        o[my_groups * 8 + k] = (uint8_t)e;
+        if (kBits == 8) o[my_groups * 8 + k] = (uint8_t)e;
+        else acc |= (uint64_t)(e & 0xFFu) << (k * kBits);
         A = __builtin_amdgcn_alignbit(A, B, s);
         B = __builtin_amdgcn_alignbit(B, Cw, s);
         Cw = __builtin_amdgcn_alignbit(Cw, 0u, s);
         L.pm1 += 32u - s;
+      }
+      if (kBits != 8) {  // whole bytes; the last one zero padded
+        QLC_GLOBAL uint8_t* d = o + my_groups * kBits;
+        for (uint32_t b = 0; b < (rem * kBits + 7) / 8; ++b) d[b] = (uint8_t)(acc >> (8 * b));
       }
     }
     if (live) bad = (L.errbits & 0x8000u) || (L.pm1 + 1 != end);
@@ -1223,6 +1427,7 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
   return bad;
 }
 
+template <int kBits>
 __global__ __launch_bounds__(kDecThreads) void k_decode(
     const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
     const uint64_t* __restrict__ index, uint32_t log2_chunk,
@@ -1233,11 +1438,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
   uint32_t sh_lo, sh_hi;
   build_dec_lut(table, S.lut, sh_lo, sh_hi);
   __syncthreads();
-  const bool bad = decode_block(bits, *total_p, index, log2_chunk, n, out, blockIdx.x, sh_lo,
-                                sh_hi, S, tid);
+  // a table of another alphabet is refused (nothing decoded)
+  if (mode_symbol_bits(table->mode) == kBits) {
+    const bool bad = decode_block<kBits>(bits, *total_p, index, log2_chunk, n, out, blockIdx.x,
+                                         sh_lo, sh_hi, S, tid);
+    set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
+  } else if (tid == 0) {
+    set_error(&hdr->dec_err, QLC_ERR_INVALID_ARGUMENT);
+  }
 
   // ---- error word: first error wins; the last workgroup publishes it ----
-  set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
   __syncthreads();
   if (tid == 0) {
     const uint32_t done = atomic_add_u32(&hdr->dec_done, 1u);
@@ -1420,6 +1630,7 @@ union BatchEncSmem {
 };
 
 // At most 128 VGPRs, so that four workgroups share a CU (LDS allows it).
+template <int kBits>
 __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
     const qlc_job* __restrict__ jobs, uint32_t mode, uint32_t log2_seg, uint32_t log2_chunk,
     BatchHeader* __restrict__ hdr, BatchJobState* __restrict__ js,
@@ -1448,7 +1659,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
       // ---- H(g): the segment's histogram; the job's last one builds the table ----
       for (uint32_t i = tid; i < 256 * kHistCopies; i += kEncThreads) S.sub[i] = 0;
       __syncthreads();
-      hist_segment(jb.in, seg0, seg1, S.sub, opaque_tid());
+      hist_segment<kBits>(jb.in, seg0, seg1, S.sub, opaque_tid());
       __syncthreads();
       const uint32_t v = hist_bin_total(S.sub, tid);
       store_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid], v);
@@ -1477,15 +1688,18 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
       }
       for (uint32_t w = tid; w < sizeof(S.enc.words) / 4; w += kEncThreads) (&S.enc.words[0][0])[w] = 0;
       __syncthreads();
+      const uint32_t* tw = reinterpret_cast<const uint32_t*>(jb.table);
       if (tid < 128) {
-        const uint32_t* tw = reinterpret_cast<const uint32_t*>(jb.table);
         const uint32_t w = load_relaxed_u32(&tw[tid]);
         S.enc.lut[2 * tid] = enc_entry(w & 0xFFFFu);
         S.enc.lut[2 * tid + 1] = enc_entry(w >> 16);
       }
+      if (tid == 0 &&
+          mode_symbol_bits(load_relaxed_u32(&tw[offsetof(qlc_table, mode) / 4])) != kBits)
+        S.enc.bad_table = 1;  // a table of another alphabet
       __syncthreads();
       const uint32_t len_t = S.enc.lut[tid] >> 16;
-      if (len_t < 2 || len_t > QLC_MAX_CODE_BITS) S.enc.bad_table = 1;
+      if (tid < Sym<kBits>::kM && (len_t < 1 || len_t > QLC_MAX_CODE_BITS)) S.enc.bad_table = 1;
       const uint64_t my_bits = block_sum_u64(
           (uint64_t)load_relaxed_u32(&seg_hist[(uint64_t)g * 256 + tid]) * len_t, S.enc.red);
       const bool bad_table = S.enc.bad_table != 0;
@@ -1501,9 +1715,9 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
       if (last_seg && tid == 0) *jb.total_bits = G0 + my_bits;
       bool cap = false;
       if (!bad_table)
-        cap = encode_segment(jb.in, seg0, seg1, G0, last_seg, log2_chunk,
-                             reinterpret_cast<uint32_t*>(jb.bits), jb.bits_capacity / 4,
-                             jb.chunk_index, S.enc, opaque_tid());
+        cap = encode_segment<kBits>(jb.in, seg0, seg1, G0, last_seg, log2_chunk,
+                                    reinterpret_cast<uint32_t*>(jb.bits), jb.bits_capacity / 4,
+                                    jb.chunk_index, S.enc, opaque_tid());
       if (cap) S.enc.cap_hit = 1;
       __syncthreads();
       if (tid == 0) {
@@ -1515,6 +1729,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
   }
 }
 
+template <int kBits>
 __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     const qlc_job* __restrict__ jobs, uint32_t log2_chunk, BatchHeader* __restrict__ hdr,
     const BatchJobState* __restrict__ js, const uint32_t* __restrict__ grp_job) {
@@ -1523,6 +1738,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
   const uint32_t tid = threadIdx.x;
   const uint32_t units = hdr->units;
   uint32_t cur = ~0u, sh_lo = 0, sh_hi = 0;
+  bool tab_ok = false;
   for (;;) {
     if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
     __syncthreads();
@@ -1532,12 +1748,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     const qlc_job jb = jobs[k];
     if (k != cur) {
       build_dec_lut(jb.table, S.lut, sh_lo, sh_hi);
+      tab_ok = mode_symbol_bits(jb.table->mode) == kBits;
       __syncthreads();
       cur = k;
     }
-    const bool bad = decode_block(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk, jb.n,
-                                  jb.out, p - js[k].base, sh_lo, sh_hi, S, opaque_tid());
-    set_error_wave(jb.err, QLC_ERR_CORRUPT_STREAM, bad);
+    if (tab_ok) {
+      const bool bad = decode_block<kBits>(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk,
+                                           jb.n, jb.out, p - js[k].base, sh_lo, sh_hi, S,
+                                           opaque_tid());
+      set_error_wave(jb.err, QLC_ERR_CORRUPT_STREAM, bad);
+    } else if (tid == 0) {
+      set_error(jb.err, QLC_ERR_INVALID_ARGUMENT);  // a table of another alphabet
+    }
     __syncthreads();
   }
 }
@@ -1558,12 +1780,24 @@ __global__ void k_zero_words(uint32_t* __restrict__ p, uint64_t nwords) {
 // ===========================================================================
 namespace qlc {
 
-hipError_t launch_histogram(const uint8_t* in, uint64_t n, WsHeader* hdr, uint64_t* xcd_part,
-                            uint32_t* seg_hist, uint64_t* hist_out, uint32_t flags, uint32_t mode,
-                            qlc_table* table_out, hipStream_t stream) {
+// Launch `kern<B>` for the symbol width B = bits (4, 6 or 8).
+#define QLC_LAUNCH_BITS(bits, kern, grid, block, ...)                                      \
+  do {                                                                                  \
+    if ((bits) == 4)                                                                    \
+      hipLaunchKernelGGL(kern<4>, grid, block, 0, stream, __VA_ARGS__);                 \
+    else if ((bits) == 6)                                                               \
+      hipLaunchKernelGGL(kern<6>, grid, block, 0, stream, __VA_ARGS__);                 \
+    else                                                                                \
+      hipLaunchKernelGGL(kern<8>, grid, block, 0, stream, __VA_ARGS__);                 \
+  } while (0)
+
+hipError_t launch_histogram(const uint8_t* in, uint64_t n, uint32_t bits, WsHeader* hdr,
+                            uint64_t* xcd_part, uint32_t* seg_hist, uint64_t* hist_out,
+                            uint32_t flags, uint32_t mode, qlc_table* table_out,
+                            hipStream_t stream) {
   const uint32_t l = seg_log2(n);
-  hipLaunchKernelGGL(k_histogram, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), 0, stream, in,
-                     n, l, hdr, xcd_part, seg_hist, hist_out, flags, mode, table_out);
+  QLC_LAUNCH_BITS(bits, k_histogram, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), in, n, l,
+                  hdr, xcd_part, seg_hist, hist_out, flags, mode, table_out);
   return hipGetLastError();
 }
 
@@ -1573,33 +1807,33 @@ hipError_t launch_table_from_hist(const uint64_t* hist, uint32_t mode, qlc_table
   return hipGetLastError();
 }
 
-hipError_t launch_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
+hipError_t launch_encode(const uint8_t* in, uint64_t n, uint32_t bits, const qlc_table* table,
                          const uint32_t* seg_hist, const uint64_t* seg_bits, uint32_t log2_chunk,
                          uint32_t* bits_out, uint64_t cap_words, uint64_t* index_out,
                          uint64_t* total_out, uint32_t* err_out, WsHeader* hdr, uint64_t* seg_word,
                          hipStream_t stream) {
   const uint32_t nseg = (uint32_t)seg_count(n);
-  hipLaunchKernelGGL(k_encode, dim3(nseg), dim3(kEncThreads), 0, stream, in, n, seg_log2(n), table,
-                     seg_hist, seg_bits, log2_chunk, bits_out, cap_words, index_out, total_out,
-                     err_out, hdr, seg_word, nseg);
+  QLC_LAUNCH_BITS(bits, k_encode, dim3(nseg), dim3(kEncThreads), in, n, seg_log2(n), table,
+                  seg_hist, seg_bits, log2_chunk, bits_out, cap_words, index_out, total_out,
+                  err_out, hdr, seg_word, nseg);
   return hipGetLastError();
 }
 
-hipError_t launch_segment_bits(const uint8_t* in, uint64_t n, const qlc_table* table,
-                               uint64_t* seg_bits, hipStream_t stream) {
-  hipLaunchKernelGGL(k_segment_bits, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), 0, stream,
-                     in, n, seg_log2(n), table, seg_bits);
+hipError_t launch_segment_bits(const uint8_t* in, uint64_t n, uint32_t bits,
+                               const qlc_table* table, uint64_t* seg_bits, hipStream_t stream) {
+  QLC_LAUNCH_BITS(bits, k_segment_bits, dim3((uint32_t)seg_count(n)), dim3(kHistThreads), in, n,
+                  seg_log2(n), table, seg_bits);
   return hipGetLastError();
 }
 
-hipError_t launch_decode(const uint8_t* bits, const uint64_t* total, const uint64_t* index,
-                         uint32_t log2_chunk, const qlc_table* table, uint64_t n, uint8_t* out,
-                         uint32_t* err_out, WsHeader* hdr, hipStream_t stream) {
+hipError_t launch_decode(const uint8_t* bits_in, const uint64_t* total, const uint64_t* index,
+                         uint32_t log2_chunk, const qlc_table* table, uint64_t n, uint32_t bits,
+                         uint8_t* out, uint32_t* err_out, WsHeader* hdr, hipStream_t stream) {
   const uint64_t nchunks = (n + (1ull << log2_chunk) - 1) >> log2_chunk;
   uint64_t blocks = (nchunks + kDecThreads - 1) / kDecThreads;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_decode, dim3((uint32_t)blocks), dim3(kDecThreads), 0, stream, bits, total,
-                     index, log2_chunk, table, n, out, err_out, hdr);
+  QLC_LAUNCH_BITS(bits, k_decode, dim3((uint32_t)blocks), dim3(kDecThreads), bits_in, total,
+                  index, log2_chunk, table, n, out, err_out, hdr);
   return hipGetLastError();
 }
 
@@ -1614,29 +1848,30 @@ hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, 
   return hipGetLastError();
 }
 
-hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t mode, uint32_t log2_seg,
-                                 uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
-                                 uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,
-                                 uint32_t* seg_hist, uint32_t grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_encode_batched, dim3(grid), dim3(kEncThreads), 0, stream, jobs, mode,
-                     log2_seg, log2_chunk, hdr, js, job_hist, seg_job, seg_word, seg_hist);
+hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t bits, uint32_t mode,
+                                 uint32_t log2_seg, uint32_t log2_chunk, BatchHeader* hdr,
+                                 BatchJobState* js, uint64_t* job_hist, const uint32_t* seg_job,
+                                 uint64_t* seg_word, uint32_t* seg_hist, uint32_t grid,
+                                 hipStream_t stream) {
+  QLC_LAUNCH_BITS(bits, k_encode_batched, dim3(grid), dim3(kEncThreads), jobs, mode, log2_seg,
+                  log2_chunk, hdr, js, job_hist, seg_job, seg_word, seg_hist);
   return hipGetLastError();
 }
 
-hipError_t launch_decode_batched(const qlc_job* jobs, uint32_t log2_chunk, BatchHeader* hdr,
-                                 const BatchJobState* js, const uint32_t* grp_job, uint32_t grid,
-                                 hipStream_t stream) {
-  hipLaunchKernelGGL(k_decode_batched, dim3(grid), dim3(kDecThreads), 0, stream, jobs, log2_chunk,
-                     hdr, js, grp_job);
+hipError_t launch_decode_batched(const qlc_job* jobs, uint32_t bits, uint32_t log2_chunk,
+                                 BatchHeader* hdr, const BatchJobState* js,
+                                 const uint32_t* grp_job, uint32_t grid, hipStream_t stream) {
+  QLC_LAUNCH_BITS(bits, k_decode_batched, dim3(grid), dim3(kDecThreads), jobs, log2_chunk, hdr,
+                  js, grp_job);
   return hipGetLastError();
 }
 
 int batched_blocks_per_cu(bool decode) {
   int nb = 0;
   hipError_t e = decode ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb, reinterpret_cast<const void*>(k_decode_batched), kDecThreads, 0)
+                              &nb, reinterpret_cast<const void*>(k_decode_batched<8>), kDecThreads, 0)
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                              &nb, reinterpret_cast<const void*>(k_encode_batched), kEncThreads, 0);
+                              &nb, reinterpret_cast<const void*>(k_encode_batched<8>), kEncThreads, 0);
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

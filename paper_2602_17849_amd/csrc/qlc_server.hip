@@ -331,7 +331,8 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
   qlc_server_config c = *h_config;
   const uint32_t C = c.chunk_symbols;
   if (c.memory_budget_bytes == 0 || C < QLC_MIN_CHUNK || C > QLC_MAX_CHUNK || (C & (C - 1)) ||
-      !valid_layout_mode(c.layout_mode) || c.max_jobs_per_tick > kMaxJobs ||
+      !valid_layout_mode(c.layout_mode) || mode_symbol_bits(c.layout_mode) != 8 ||
+      c.max_jobs_per_tick > kMaxJobs ||
       c.max_ticks_in_flight > kMaxTicks || c.reserved ||
       (c.log2_segment && (c.log2_segment < 13 || c.log2_segment > 24)))
     return QLC_ERR_INVALID_ARGUMENT;

@@ -182,3 +182,43 @@ def stress_buffer(kind: str, numel: int = 1 << 32, device="cpu",
 
 def sha256(x: torch.Tensor) -> str:
     return hashlib.sha256(x.detach().cpu().contiguous().numpy().tobytes()).hexdigest()
+
+
+# ------------------------------------------------------- packed small symbols
+def pack_symbols(codes: np.ndarray, bits: int) -> np.ndarray:
+    """Pack symbols of `bits` bits (4 or 6; 8 returns a copy) into bytes in
+    little-endian bit order: symbol i occupies bits bits*i .. bits*i + bits - 1
+    of the byte string read least significant bit first (for 4 bits: symbol
+    2k is the low nibble of byte k).  Pad bits are zero."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint8).reshape(-1)
+    if bits == 8:
+        return codes.copy()
+    assert int(codes.max(initial=0)) < (1 << bits)
+    b = np.unpackbits(codes[:, None], axis=1, bitorder="little")[:, :bits].reshape(-1)
+    return np.packbits(b, bitorder="little")
+
+
+def unpack_symbols(packed: np.ndarray, n: int, bits: int) -> np.ndarray:
+    """Inverse of pack_symbols: n symbols, one per byte."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if bits == 8:
+        return packed[:n].copy()
+    b = np.unpackbits(packed, bitorder="little")[:n * bits].reshape(n, bits)
+    return np.packbits(b, axis=1, bitorder="little").reshape(-1)
+
+
+def small_float_codes(n: int, mant_bits: int, exp_bits: int, seed: int) -> np.ndarray:
+    """Codes of a small sign/exponent/mantissa float type (e2m1: 1, 2;
+    e3m2: 2, 3) for Laplace(0, 1) samples, rounded to the nearest
+    representable magnitude; one code per byte, below 2^(1 + exp + mant)."""
+    rng = np.random.default_rng(seed)
+    v = rng.laplace(0.0, 1.0, n)
+    mags = []
+    for e in range(1 << exp_bits):
+        for m in range(1 << mant_bits):
+            frac = m / (1 << mant_bits)
+            mags.append(frac if e == 0 else (1 + frac) * 2.0 ** (e - 1))
+    mags = np.array(mags)
+    idx = np.abs(np.abs(v)[:, None] - mags[None, :]).argmin(1)
+    half = len(mags)
+    return (idx + half * (v < 0)).astype(np.uint8)

@@ -32,6 +32,21 @@ LAYOUT_PAPER_T2 = 3
 
 
 LAYOUT_SEARCH_AREAS4 = 32   # 2-bit area code, 4 areas
+# small alphabets (the *_sym entry points): 16 symbols (4-bit) or 64 (6-bit)
+LAYOUT_M16_AREAS2 = 48
+LAYOUT_M16_AREAS4 = 49
+LAYOUT_M64_AREAS4 = 50
+LAYOUT_M64_AREAS8 = 51
+
+
+def mode_symbol_bits(mode: int) -> int:
+    """Bits per symbol of the alphabet a layout mode codes."""
+    return 4 if mode in (48, 49) else 6 if mode in (50, 51) else 8
+
+
+def packed_bytes(n: int, symbol_bits: int) -> int:
+    """Bytes holding n packed symbols of symbol_bits bits."""
+    return (n * symbol_bits + 7) // 8
 
 
 def LAYOUT_SEARCH_DISTINCT(k: int) -> int:
@@ -122,6 +137,18 @@ _SIGNATURES = {
     "qlc_compress_noalloc": ([_vp, _u64, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp],
                              ctypes.c_int),
     "qlc_decode": ([_vp, _vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_histogram_sym": ([_vp, _u64, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_histogram_accumulate_sym": ([_vp, _u64, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_build_table_sym": ([_vp, _u64, _u32, ctypes.c_int, _vp, _vp, _sz, _vp], ctypes.c_int),
+    "qlc_compress_sym": ([_vp, _u64, _u32, ctypes.c_int, _vp, _u32, _vp, _u64, _vp, _vp, _vp,
+                          _vp, _sz, _vp], ctypes.c_int),
+    "qlc_encode_sym": ([_vp, _u64, _u32, _vp, _u32, _vp, _u64, _vp, _vp, _vp, _vp, _sz, _vp],
+                       ctypes.c_int),
+    "qlc_decode_sym": ([_vp, _vp, _vp, _u32, _vp, _u64, _u32, _vp, _vp, _vp, _sz, _vp],
+                       ctypes.c_int),
+    "qlc_encode_batched_sym": ([_vp, _u32, _u32, ctypes.c_int, _u32, _vp, _vp, _sz, _vp],
+                               ctypes.c_int),
+    "qlc_decode_batched_sym": ([_vp, _u32, _u32, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_batched_workspace_bytes": ([_u32, _u64, _u32, _vp], _sz),
     "qlc_encode_batched": ([_vp, _u32, ctypes.c_int, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
     "qlc_decode_batched": ([_vp, _u32, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -275,6 +302,69 @@ def qlc_decode(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor, chu
                ws: torch.Tensor, stream=None):
     _check(lib().qlc_decode(_p(bits), _p(total), _p(index), chunk_symbols, _p(table), n, _p(out),
                             _p(err_out), _p(ws), _nbytes(ws), _stream(stream)), "qlc_decode")
+
+
+# ------------------------------------------------------------ small alphabets
+# n counts symbols; tensors hold the packed bytes (see include/qlc.h).
+def qlc_histogram_sym(x: torch.Tensor, n: int, symbol_bits: int, hist_out: torch.Tensor,
+                      ws: torch.Tensor, stream=None):
+    _check(lib().qlc_histogram_sym(_p(x), n, symbol_bits, _p(hist_out), _p(ws), _nbytes(ws),
+                                   _stream(stream)), "qlc_histogram_sym")
+
+
+def qlc_histogram_accumulate_sym(x: torch.Tensor, n: int, symbol_bits: int,
+                                 hist_inout: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_histogram_accumulate_sym(_p(x), n, symbol_bits, _p(hist_inout), _p(ws),
+                                              _nbytes(ws), _stream(stream)),
+           "qlc_histogram_accumulate_sym")
+
+
+def qlc_build_table_sym(x: torch.Tensor, n: int, symbol_bits: int, mode: int,
+                        table_out: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_build_table_sym(_p(x), n, symbol_bits, mode, _p(table_out), _p(ws),
+                                     _nbytes(ws), _stream(stream)), "qlc_build_table_sym")
+
+
+def qlc_compress_sym(x: torch.Tensor, n: int, symbol_bits: int, mode: int,
+                     table_out: torch.Tensor, chunk_symbols: int, bits_out: torch.Tensor,
+                     index_out: torch.Tensor, total_out: torch.Tensor, err_out: torch.Tensor,
+                     ws: torch.Tensor, stream=None):
+    _check(lib().qlc_compress_sym(_p(x), n, symbol_bits, mode, _p(table_out), chunk_symbols,
+                                  _p(bits_out), _nbytes(bits_out), _p(index_out), _p(total_out),
+                                  _p(err_out), _p(ws), _nbytes(ws), _stream(stream)),
+           "qlc_compress_sym")
+
+
+def qlc_encode_sym(x: torch.Tensor, n: int, symbol_bits: int, table: torch.Tensor,
+                   chunk_symbols: int, bits_out: torch.Tensor, index_out: torch.Tensor,
+                   total_out: torch.Tensor, err_out: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_encode_sym(_p(x), n, symbol_bits, _p(table), chunk_symbols, _p(bits_out),
+                                _nbytes(bits_out), _p(index_out), _p(total_out), _p(err_out),
+                                _p(ws), _nbytes(ws), _stream(stream)), "qlc_encode_sym")
+
+
+def qlc_decode_sym(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor,
+                   chunk_symbols: int, table: torch.Tensor, n: int, symbol_bits: int,
+                   out: torch.Tensor, err_out: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_decode_sym(_p(bits), _p(total), _p(index), chunk_symbols, _p(table), n,
+                                symbol_bits, _p(out), _p(err_out), _p(ws), _nbytes(ws),
+                                _stream(stream)), "qlc_decode_sym")
+
+
+def qlc_encode_batched_sym(jobs: torch.Tensor, n_jobs: int, symbol_bits: int, mode: int,
+                           chunk_symbols: int, ws: torch.Tensor, tuning=None, stream=None):
+    keep, tp = _tuning_ptr(tuning)
+    _check(lib().qlc_encode_batched_sym(_p(jobs), n_jobs, symbol_bits, mode, chunk_symbols, tp,
+                                        _p(ws), _nbytes(ws), _stream(stream)),
+           "qlc_encode_batched_sym")
+
+
+def qlc_decode_batched_sym(jobs: torch.Tensor, n_jobs: int, symbol_bits: int,
+                           chunk_symbols: int, ws: torch.Tensor, tuning=None, stream=None):
+    keep, tp = _tuning_ptr(tuning)
+    _check(lib().qlc_decode_batched_sym(_p(jobs), n_jobs, symbol_bits, chunk_symbols, tp,
+                                        _p(ws), _nbytes(ws), _stream(stream)),
+           "qlc_decode_batched_sym")
 
 
 def _tuning_ptr(tuning):

@@ -289,10 +289,11 @@ def test_capacity_error():
     assert not bits[cap:].any()          # nothing written past the capacity
 
 
-@pytest.mark.parametrize("sym,length", [(0, 0), (131, 12), (255, 1)])
+@pytest.mark.parametrize("sym,length", [(0, 0), (131, 12), (255, 31)])
 def test_bad_table_rejected(sym, length):
-    """A given table with a code length outside 2..11 is rejected by every
-    workgroup of the encode (device error word), plain and batched."""
+    """A given table with a code length outside 1..11 is rejected by every
+    workgroup of the encode (device error word), plain and batched.  (One-bit
+    codes are legal: a two-area table of 16 symbols has them.)"""
     n = 5_000_000
     x = datagen.gaussian(n, 13).numpy()
     t = table_from_oracle(oracle.build_table(oracle.histogram(x), 0))
@@ -337,23 +338,6 @@ def test_table_from_oversized_histogram_is_unusable(case):
     assert_table_equal(t, oracle.build_table(below, qlc.LAYOUT_SEARCH_QUAD))
 
 
-def _small_float_codes(n, mant_bits, exp_bits, seed):
-    """Codes of a small sign/exponent/mantissa float type (one code per byte,
-    values below 2^(1 + exp_bits + mant_bits)) for Laplace(0, 1) samples,
-    rounded to the nearest representable magnitude."""
-    rng = np.random.default_rng(seed)
-    v = rng.laplace(0.0, 1.0, n)
-    mags = []
-    for e in range(1 << exp_bits):
-        for m in range(1 << mant_bits):
-            frac = m / (1 << mant_bits)
-            mags.append(frac if e == 0 else (1 + frac) * 2.0 ** (e - 1))
-    mags = np.array(mags)
-    idx = np.abs(np.abs(v)[:, None] - mags[None, :]).argmin(1)
-    half = len(mags)
-    return (idx + half * (v < 0)).astype(np.uint8)
-
-
 @pytest.mark.parametrize("fmt", [(1, 2), (2, 3)])        # e2m1 (16 codes), e3m2 (64 codes)
 @pytest.mark.parametrize("mode", [qlc.LAYOUT_SEARCH_QUAD, qlc.LAYOUT_SEARCH_ANY,
                                   qlc.LAYOUT_SEARCH_AREAS4])
@@ -363,7 +347,7 @@ def test_small_alphabets_one_code_per_byte(fmt, mode):
     layout mode applies unchanged; table, stream and index equal the
     oracle's and the decode restores every code."""
     mant, exp = fmt
-    x = _small_float_codes(200003, mant, exp, seed=21 + mant)
+    x = datagen.small_float_codes(200003, mant, exp, seed=21 + mant)
     assert int(x.max()) < (1 << (1 + exp + mant))
     h = oracle.histogram(x)
     if mode == qlc.LAYOUT_SEARCH_AREAS4:

@@ -182,3 +182,58 @@ def test_distinct_caps_nest():
             a, b = oracle.build_table_general(h, 256, 8, 3, k), oracle.build_table(h, mode)
             assert list(a.width) == list(b.width) and a.cost_bits == b.cost_bits
             assert list(a.code) == list(b.code) and list(a.len) == list(b.len)
+
+
+def composition_brute_force_min_cost(h, M, A, prefix_bits):
+    """Min over every split of the M symbols into A non-empty areas of any
+    sizes (not only powers of two, not only greedy fills): for given area
+    sizes n_a the cheapest assignment puts the most frequent symbols in the
+    areas of fewest suffix bits (rearrangement inequality), so the search
+    runs over all compositions n_0 + ... + n_{A-1} = M with n_a >= 1."""
+    h = np.sort(np.asarray(h, dtype=np.int64))[::-1]          # most frequent first
+    prefix = np.concatenate([[0], np.cumsum(h)])
+    best = None
+    # compositions of M into A positive parts = choices of A-1 cut points in 1..M-1
+    cuts = np.array(list(itertools.combinations(range(1, M), A - 1)), dtype=np.int64)
+    step = 1 << 16
+    for lo in range(0, len(cuts), step):
+        c = cuts[lo:lo + step]
+        edges = np.concatenate([np.zeros((len(c), 1), np.int64), c,
+                                np.full((len(c), 1), M, np.int64)], 1)
+        sizes = np.diff(edges, axis=1)                          # [k, A] area sizes
+        widths = np.ceil(np.log2(sizes)).astype(np.int64)
+        # symbols sorted by frequency go to areas sorted by width
+        order = np.argsort(widths, axis=1, kind="stable")
+        sw = np.take_along_axis(widths, order, 1)
+        ss = np.take_along_axis(sizes, order, 1)
+        ends = np.cumsum(ss, axis=1)
+        starts = ends - ss
+        counts = prefix[ends] - prefix[starts]
+        cost = (counts * (prefix_bits + sw)).sum(1)
+        m = int(cost.min())
+        best = m if best is None else min(best, m)
+    return best
+
+
+@pytest.mark.parametrize("M,A,p", [(16, 4, 2), (16, 8, 3), (32, 8, 3), (64, 4, 2), (8, 4, 2)])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_search_matches_composition_brute_force(M, A, p, seed):
+    """The greedy fill over non-decreasing power-of-two width tuples loses
+    nothing against areas of arbitrary sizes: 16 and 64 symbols with 4
+    areas (the small-alphabet codecs), 8 areas of 16 and 32 symbols (the
+    3-bit area code on a non-degenerate alphabet)."""
+    rng = np.random.default_rng(seed * 31 + M + A)
+    h = (rng.pareto(rng.uniform(0.5, 2.0), size=M) * 1000).astype(np.int64)
+    h[rng.integers(0, M)] = 0
+    t = oracle.build_table_general(h, M, A, p, A)
+    assert t.cost_bits == composition_brute_force_min_cost(h, M, A, p)
+
+
+def test_composition_brute_force_agrees_with_map_brute_force():
+    """The composition search equals the search over every symbol -> area
+    map where both are feasible."""
+    rng = np.random.default_rng(77)
+    for M, A, p in ((8, 2, 1), (8, 3, 2), (8, 4, 2)):
+        h = (rng.pareto(1.0, size=M) * 100).astype(np.int64)
+        assert composition_brute_force_min_cost(h, M, A, p) == \
+            brute_force_min_cost(h, M, A, p, A, allow_empty=False)
