@@ -361,14 +361,17 @@ qlc_status qlc_decode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t
                                   uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning,
                                   void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Host-side persisted table form: width[8] followed by rank_to_sym[256]
- * (tables of the byte alphabet). */
+/* Host-side persisted table form: width[8] followed by rank_to_sym[256]. */
 qlc_status qlc_table_serialize(const qlc_table* h_table,
                                uint8_t h_out[QLC_SERIALIZED_TABLE_BYTES]);
-/* Rebuild a full table on the host (8 areas, or 4 areas when widths 4..7
- * are all 0xFF); rejects widths that are not non-decreasing in 0..8, that
- * leave an area empty or do not cover 256 ranks, and rank orders that are
- * not a permutation. */
+/* Rebuild a full table on the host: 8, 4 or 2 areas (the widths after the
+ * last area are 0xFF), over the alphabet of 256, 64 or 16 symbols that the
+ * widths fill greedily with every area non-empty (at most one does; 8
+ * areas are never a 16-symbol table).  Rejects widths that are not
+ * non-decreasing in 0..8 or fit no alphabet, and rank orders that are not
+ * a permutation of the alphabet (identity beyond it).  A 16- or 64-symbol
+ * table gets its QLC_LAYOUT_M* mode, so the *_sym calls accept it; a byte
+ * table gets mode 0xFFFFFFFF. */
 qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES],
                                  qlc_table* h_table);
 

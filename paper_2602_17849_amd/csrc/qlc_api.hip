@@ -454,9 +454,9 @@ qlc_status qlc_table_serialize(const qlc_table* h_table, uint8_t h_out[QLC_SERIA
 
 qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES], qlc_table* t) {
   if (!h_in || !t) return QLC_ERR_INVALID_ARGUMENT;
-  // 8 areas (3-bit area code), or 4 areas (2-bit code) with widths 4..7 = 0xFF
-  const uint32_t na = h_in[4] == 0xFFu ? 4u : 8u;
-  const uint32_t pbits = na == 4 ? 2u : 3u;
+  // 8, 4 or 2 areas: the widths after the last area are 0xFF
+  const uint32_t na = h_in[4] != 0xFFu ? 8u : h_in[2] != 0xFFu ? 4u : 2u;
+  const uint32_t pbits = na == 8 ? 3u : na == 4 ? 2u : 1u;
   uint32_t w[8];
   for (uint32_t a = 0; a < 8; ++a) {
     w[a] = h_in[a];
@@ -466,43 +466,64 @@ qlc_status qlc_table_deserialize(const uint8_t h_in[QLC_SERIALIZED_TABLE_BYTES],
     }
     if (w[a] > 8 || (a && w[a] < w[a - 1])) return QLC_ERR_INVALID_ARGUMENT;
   }
-  uint32_t f = 0, first[8], count[8];
-  for (uint32_t a = 0; a < 8; ++a) {
-    if (a >= na) {
-      first[a] = 256;
-      count[a] = 0;
-      continue;
+  // The alphabet: the one of 16, 64 or 256 symbols (widths at most its
+  // symbol width) whose greedy fill leaves every area non-empty and covers
+  // it; at most one fits any width tuple.
+  uint32_t M = 0, sbits = 0, first[8], count[8];
+  for (uint32_t b : {4u, 6u, 8u}) {
+    const uint32_t m = 1u << b;
+    // the layouts that exist: 16 symbols in 2 or 4 areas, 64 or 256 in 4 or 8
+    if (w[na - 1] > b || (b == 4 ? na == 8 : na == 2)) continue;
+    uint32_t f = 0;
+    bool ok = true;
+    for (uint32_t a = 0; a < na && ok; ++a) {
+      const uint32_t cap = 1u << w[a];
+      first[a] = f;
+      count[a] = cap < m - f ? cap : m - f;
+      ok = count[a] != 0;
+      f += count[a];
     }
-    const uint32_t cap = 1u << w[a];
-    first[a] = f;
-    count[a] = cap < 256 - f ? cap : 256 - f;
-    if (count[a] == 0) return QLC_ERR_INVALID_ARGUMENT;
-    f += count[a];
+    if (ok && f == m) {
+      M = m;
+      sbits = b;
+      break;
+    }
   }
-  if (f != 256) return QLC_ERR_INVALID_ARGUMENT;
+  if (M == 0) return QLC_ERR_INVALID_ARGUMENT;
+  for (uint32_t a = na; a < 8; ++a) {
+    first[a] = 256;
+    count[a] = 0;
+  }
+  // rank order: a permutation of the alphabet, identity beyond it
   bool seen[256] = {};
-  for (int r = 0; r < 256; ++r) {
-    if (seen[h_in[8 + r]]) return QLC_ERR_INVALID_ARGUMENT;
-    seen[h_in[8 + r]] = true;
+  for (uint32_t r = 0; r < 256; ++r) {
+    const uint32_t s = h_in[8 + r];
+    if (seen[s] || (r < M ? s >= M : s != r)) return QLC_ERR_INVALID_ARGUMENT;
+    seen[s] = true;
   }
   memset(t, 0, sizeof(*t));
   for (uint32_t a = 0; a < 8; ++a) {
     t->width[a] = (uint8_t)w[a];
     t->first[a] = (uint16_t)first[a];
     t->count[a] = (uint16_t)count[a];
-    t->offset[a] = (uint8_t)(a >= na || w[a] == 8 ? 0 : first[a]);
+    t->offset[a] = (uint8_t)(a >= na || w[a] == sbits ? 0 : first[a]);
   }
-  for (int r = 0; r < 256; ++r) {
+  for (uint32_t r = 0; r < 256; ++r) {
     const uint32_t s = h_in[8 + r];
     t->rank_to_sym[r] = (uint8_t)s;
     t->sym_to_rank[s] = (uint8_t)r;
+    if (r >= M) continue;  // no code outside the alphabet
     uint32_t a = 0;
-    for (uint32_t k = 1; k < na; ++k) a = (uint32_t)r >= first[k] ? k : a;
-    const uint32_t code = (a << w[a]) | ((uint32_t)r - t->offset[a]);
+    for (uint32_t k = 1; k < na; ++k) a = r >= first[k] ? k : a;
+    const uint32_t code = (a << w[a]) | (r - t->offset[a]);
     t->enc[s] = (uint16_t)(((pbits + w[a]) << 11) | code);
   }
   t->cost_bits = 0;
-  t->mode = 0xFFFFFFFFu;
+  // the small-alphabet modes name their alphabet; a byte table's search
+  // mode is not recorded
+  t->mode = M == 16 ? (na == 2 ? QLC_LAYOUT_M16_AREAS2 : QLC_LAYOUT_M16_AREAS4)
+            : M == 64 ? (na == 4 ? QLC_LAYOUT_M64_AREAS4 : QLC_LAYOUT_M64_AREAS8)
+                      : 0xFFFFFFFFu;
   t->version = QLC_ABI_VERSION;
   return QLC_OK;
 }

@@ -90,9 +90,13 @@ def test_host_table_deserialize_matches_oracle(seed):
 
 def test_host_table_deserialize_rejects_invalid():
     perm = bytes(range(256))
-    for w in ([3] * 8, [5, 5, 5, 5, 5, 5, 4, 8], [9, 3, 3, 3, 3, 4, 5, 8], [5, 5, 5, 5, 5, 5, 6, 6]):
+    # eight areas of 4 symbols cover no alphabet (32); the last area of the
+    # fourth tuple is empty for 256 symbols and its widths exceed 16 or 64
+    for w in ([2] * 8, [5, 5, 5, 5, 5, 5, 4, 8], [9, 3, 3, 3, 3, 4, 5, 8], [5, 5, 5, 5, 5, 5, 6, 6]):
         with pytest.raises(qlc.QLCError):
             qlc.qlc_table_deserialize(bytes(w) + perm)
+    # eight areas of 8 symbols are a 64-symbol table (too small for 256)
+    assert qlc.parse_table(qlc.qlc_table_deserialize(bytes([3] * 8) + perm))["mode"] == 51
     with pytest.raises(qlc.QLCError):
         qlc.qlc_table_deserialize(bytes([3, 3, 3, 3, 3, 4, 5, 8]) + bytes([0]) + perm[1:255] + bytes([0]))
     # the table the device builds from a histogram summing to 2^48 or more
@@ -174,3 +178,33 @@ def test_host_table_deserialize_four_areas(seed):
     bad[7] = 8
     with pytest.raises(qlc.QLCError):
         qlc.qlc_table_deserialize(bytes(bad))
+
+
+@pytest.mark.parametrize("M,A,p", [(16, 2, 1), (16, 4, 2), (64, 4, 2), (64, 8, 3)])
+def test_host_table_deserialize_small_alphabets(M, A, p):
+    """Tables of 16 or 64 symbols (the widths after the last area 0xFF, the
+    rank order a permutation of the alphabet and the identity beyond it)
+    rebuilt on the host: the oracle's codes and lengths for the alphabet, no
+    code outside it, the alphabet's layout mode; a rank order that leaves
+    the alphabet is refused."""
+    rng = np.random.default_rng(M + A)
+    h = (rng.pareto(1.0, M) * 100).astype(np.uint64)
+    ot = oracle.build_table_general(h, M, A, p, A)
+    widths = list(ot.width.astype(np.uint8)) + [0xFF] * (8 - A)
+    order = list(ot.rank_to_sym.astype(np.uint8)) + list(range(M, 256))
+    blob = bytes(widths) + bytes(order)
+    t = qlc.parse_table(qlc.qlc_table_deserialize(blob))
+    assert list(t["width"]) == widths
+    assert list(t["first"][:A]) == list(ot.first) and list(t["count"][:A]) == list(ot.count)
+    assert list(t["offset"][:A]) == list(ot.offset)
+    assert np.array_equal(t["enc"][:M] >> 11, ot.len) and np.array_equal(t["enc"][:M] & 0x7FF, ot.code)
+    assert not t["enc"][M:].any()
+    assert t["mode"] == {(16, 2): 48, (16, 4): 49, (64, 4): 50, (64, 8): 51}[(M, A)]
+    assert qlc.qlc_table_serialize(qlc.qlc_table_deserialize(blob)) == blob
+    for r, s in ((0, M), (M, M + 1)):          # a rank leaving the alphabet, a swap beyond it
+        bad = bytearray(blob)
+        i = 8 + r
+        j = 8 + order.index(s)
+        bad[i], bad[j] = bad[j], bad[i]
+        with pytest.raises(qlc.QLCError):
+            qlc.qlc_table_deserialize(bytes(bad))
