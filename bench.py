@@ -224,6 +224,15 @@ def run_batched(dev, steps, plain_steps=2, fixed=None):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps / 1e3
 
+    def plain_pass_lane():  # the same with the one-lane-per-chunk decoder forced
+        for x, t, bits, idx, tot, err, out, de, n in args:
+            qlc.qlc_compress(x, mode, t, C, bits, idx, tot, err, wsp)
+            qlc.qlc_decode_ex(bits, tot, idx, C, t, n, 8, qlc.DECODER_LANE, out, de, wsp)
+
+    t_plain_lane = timed(plain_pass_lane, plain_steps)
+    assert not B.err.any().item() and not derr.any().item()
+    assert torch.equal(B.out, A.inp), "plain round trip (lane decoder)"
+    B.out.zero_()
     t_plain = timed(plain_pass, plain_steps)
     g_plain = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g_plain):
@@ -264,7 +273,12 @@ def run_batched(dev, steps, plain_steps=2, fixed=None):
         "gbps": round(total / t_b / 1e9, 2),
         "encode_gbps": round(total / t_enc / 1e9, 2),
         "decode_gbps": round(total / t_dec / 1e9, 2),
+        "plain_decoders": "qlc_decode picks per shard (QLC_DECODER_AUTO); 'lane' forces "
+                          "one lane per chunk",
+        "plain_decoder_split_shards": sum(
+            qlc.qlc_decoder_choice(n, C) == qlc.DECODER_SPLIT for n in sizes),
         "plain_per_shard_gbps": round(total / t_plain / 1e9, 2),
+        "plain_per_shard_lane_gbps": round(total / t_plain_lane / 1e9, 2),
         "plain_per_shard_graph_gbps": round(total / t_plain_graph / 1e9, 2),
         "speedup_vs_plain": round(t_plain / t_b, 3),
         "speedup_vs_plain_graph": round(t_plain_graph / t_b, 3),
@@ -317,10 +331,26 @@ def run_small(dev, reps=200):
         assert int(err.item()) == 0 and int(derr.item()) == 0 and torch.equal(x, y)
         tc = float(np.median([e[0].elapsed_time(e[1]) for e in ev])) * 1e3
         td = float(np.median([e[1].elapsed_time(e[2]) for e in ev])) * 1e3
-        out["C%d" % C] = {"compress_us": round(tc, 2), "decode_us": round(td, 2),
-                          "compress_gbps": round(n / tc / 1e3, 2),
-                          "decode_gbps": round(n / td / 1e3, 2),
-                          "bits_per_symbol": round(int(total.item()) / n, 5)}
+        res = {"compress_us": round(tc, 2), "decode_us": round(td, 2),
+               "compress_gbps": round(n / tc / 1e3, 2), "decode_gbps": round(n / td / 1e3, 2),
+               "bits_per_symbol": round(int(total.item()) / n, 5),
+               "decoder": "split" if qlc.qlc_decoder_choice(n, C) == qlc.DECODER_SPLIT
+               else "lane"}
+        for name, dec in (("lane", qlc.DECODER_LANE), ("split", qlc.DECODER_SPLIT)):
+            evd = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                   for _ in range(reps // 2)]
+            for k in range(reps // 2 + 3):
+                e = evd[k - 3] if k >= 3 else None
+                if e:
+                    e[0].record(stream)
+                qlc.qlc_decode_ex(bits, total, index, C, table, n, 8, dec, y, derr, ws)
+                if e:
+                    e[1].record(stream)
+            torch.cuda.synchronize()
+            assert int(derr.item()) == 0 and torch.equal(x, y), name
+            res["decode_%s_us" % name] = round(
+                float(np.median([e[0].elapsed_time(e[1]) for e in evd])) * 1e3, 2)
+        out["C%d" % C] = res
     return out
 
 

@@ -241,6 +241,40 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits,
                       uint32_t* err_out, void* ws, size_t ws_bytes,
                       hipStream_t stream);
 
+/* Step 6 with a choice of decoder.  Both give the same output and errors
+ * (the decoding section of the paper: each code's length follows from its
+ * area code, so a chunk can also be cut into pieces whose code boundaries
+ * are found by walking lengths alone):
+ *   QLC_DECODER_LANE   one lane walks each chunk from its index entry; the
+ *                      rate for tensors of many chunks (n / C >= 2^17);
+ *   QLC_DECODER_SPLIT  C / 64 lanes per chunk (C <= 16384, else
+ *                      QLC_ERR_INVALID_ARGUMENT): each lane walks the code
+ *                      lengths of one piece of the chunk's bits from a
+ *                      guessed start, the lanes correct their starts from
+ *                      their neighbours' exits, then each decodes about 64
+ *                      codes; latency for tensors of few chunks;
+ *   QLC_DECODER_AUTO   the one qlc_decode / qlc_decode_sym use: the decoder
+ *                      with the shorter estimated time, from models of both
+ *                      fitted on MI355X (256 MiB down to 1 Mi symbols):
+ *                      LANE  max(14.6 us + 36.7 ns * C, 0.615 ps * n),
+ *                      SPLIT 25 us + 1.28 ps * n (only for C <= 16384).
+ * symbol_bits as in the *_sym entry points below (8 for bytes); other
+ * arguments and errors as qlc_decode. */
+typedef enum qlc_decoder {
+  QLC_DECODER_AUTO = 0,
+  QLC_DECODER_LANE = 1,
+  QLC_DECODER_SPLIT = 2
+} qlc_decoder;
+/* The decoder QLC_DECODER_AUTO takes for n symbols at chunk size C:
+ * QLC_DECODER_LANE or QLC_DECODER_SPLIT (QLC_DECODER_AUTO for an invalid C).
+ * Host only, no device call. */
+qlc_decoder qlc_decoder_choice(uint64_t n, uint32_t chunk_symbols);
+qlc_status qlc_decode_ex(const uint8_t* bits, const uint64_t* total_bits,
+                         const uint64_t* chunk_index, uint32_t chunk_symbols,
+                         const qlc_table* table, uint64_t n, uint32_t symbol_bits,
+                         qlc_decoder decoder, uint8_t* out, uint32_t* err_out,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- Small alphabets: 4-bit and 6-bit symbols, packed ----
  *
  * The *_sym entry points take `symbol_bits` = 4, 6 or 8 and otherwise the

@@ -26,6 +26,12 @@ hipError_t launch_segment_bits(const uint8_t* in, uint64_t n, uint32_t bits,
 hipError_t launch_decode(const uint8_t* bits_in, const uint64_t* total, const uint64_t* index,
                          uint32_t log2_chunk, const qlc_table* table, uint64_t n, uint32_t bits,
                          uint8_t* out, uint32_t* err_out, WsHeader* hdr, hipStream_t stream);
+// Several lanes per chunk (log2_chunk <= kSplitMaxLog2Chunk).
+constexpr uint32_t kSplitMaxLog2Chunk = 14;
+hipError_t launch_decode_split(const uint8_t* bits_in, const uint64_t* total, const uint64_t* index,
+                               uint32_t log2_chunk, const qlc_table* table, uint64_t n,
+                               uint32_t bits, uint8_t* out, uint32_t* err_out, WsHeader* hdr,
+                               hipStream_t stream);
 hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
                              uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
                              uint64_t* job_hist, uint32_t* unit_job, uint64_t* seg_word,

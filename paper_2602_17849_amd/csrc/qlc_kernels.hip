@@ -1137,43 +1137,113 @@ __device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __rest
   return pack_group(e, L.errbits);
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads in flight
+// stay in flight across it (__syncthreads() would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Copy a table (device memory, 16-byte aligned) into LDS: one 16-byte load
+// per lane of the first 68 lanes, so the LUT build below reads LDS instead
+// of waiting on a global load for every entry.  The caller synchronises
+// before reading the copy.
+static_assert(sizeof(qlc_table) % 16 == 0, "table copied in 16-byte pieces");
+__device__ __forceinline__ void table_to_lds(const qlc_table* __restrict__ t, qlc_table* s,
+                                             uint32_t tid) {
+  if (tid < sizeof(qlc_table) / 16) ((uint4*)s)[tid] = ((const uint4*)t)[tid];
+}
+
 // Code -> symbol LUT of `table` into `lut` (2048 32-bit entries, bit 15 =
 // invalid suffix) and the shift table indexed by the window's top three
 // bits (byte i of sh_hi:sh_lo = 32 - prefix bits - width of the area the
 // top bits name).  A table whose areas 4..7 (or 2..7) are marked 0xFF has a
 // 2-bit (1-bit) area code: top bits 2a and 2a + 1 (4a .. 4a + 3) all name
 // area a, so the decode chain is the same for every prefix width.  Any
-// block size; the caller synchronises before using the LUT.
+// block size; every thread of the block calls it (it may synchronise the
+// block), and the caller synchronises again before using the LUT.
+// The per-area fields of a table (width, offset, first, count: 48
+// contiguous bytes), read with three 16-byte loads.
+static_assert(offsetof(qlc_table, width) == 1024 && offsetof(qlc_table, offset) == 1032 &&
+                  offsetof(qlc_table, first) == 1040 && offsetof(qlc_table, count) == 1056,
+              "table layout");
+struct AreaFields {
+  uint32_t p, na;                   // area-code bits, areas
+  uint32_t w[8], off[8], first[8], cnt[8];
+};
+__device__ __forceinline__ AreaFields read_areas(const qlc_table* __restrict__ table) {
+  const uint4* q = (const uint4*)&table->width[0];
+  const uint4 a = q[0], b = q[1], c = q[2];
+  AreaFields f;
+  const uint32_t wd[2] = {a.x, a.y}, of[2] = {a.z, a.w};
+  const uint32_t fi[4] = {b.x, b.y, b.z, b.w}, co[4] = {c.x, c.y, c.z, c.w};
+  const uint32_t w4 = (wd[1] & 0xFFu), w2 = (wd[0] >> 16) & 0xFFu;
+  f.p = w4 != 0xFFu ? 3u : w2 != 0xFFu ? 2u : 1u;
+  f.na = 1u << f.p;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t wk = (wd[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+    f.w[k] = (uint32_t)k < f.na ? (wk < 8 ? wk : 8u) : 0u;  // keeps codes < 2048
+    f.off[k] = (of[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+    f.first[k] = (fi[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+    f.cnt[k] = (uint32_t)k < f.na ? (co[k >> 1] >> (16 * (k & 1))) & 0xFFFFu : 0u;
+  }
+  return f;
+}
+
 __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ table, uint32_t* lut,
                               uint32_t& sh_lo, uint32_t& sh_hi) {
   sh_lo = 0;
   sh_hi = 0;
-  {
-    const uint32_t p = table->width[4] != 0xFFu ? 3u : table->width[2] != 0xFFu ? 2u : 1u;
-    const uint32_t na = 1u << p;
-    uint32_t w[8], lo[8], off[8], first[8], cnt[8];
+  const AreaFields A = read_areas(table);
+  const uint32_t p = A.p, na = A.na;
+  uint32_t lo[8];
+  bool layered = true;  // widths non-decreasing, rank ranges back to back
+  uint32_t f = 0;
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const uint32_t wa = table->width[a];
-      w[a] = (uint32_t)a < na ? (wa < 8 ? wa : 8u) : 0u;  // keeps codes < 2048
-      off[a] = table->offset[a];
-      first[a] = table->first[a];
-      cnt[a] = (uint32_t)a < na ? table->count[a] : 0u;
-      lo[a] = (uint32_t)a << w[a];
+  for (int a = 0; a < 8; ++a) {
+    lo[a] = (uint32_t)a << A.w[a];
+    if ((uint32_t)a < na) {
+      layered = layered && A.first[a] == f && (a == 0 || A.w[a] >= A.w[a - 1]);
+      f += A.cnt[a];
     }
+  }
+  layered = layered && f <= 256;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint32_t sft = 32u - p - w[i >> (3 - p)];
-      if (i < 4) sh_lo |= sft << (8 * i);
-      else sh_hi |= sft << (8 * (i - 4));
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t sft = 32u - p - A.w[i >> (3 - p)];
+    if (i < 4) sh_lo |= sft << (8 * i);
+    else sh_hi |= sft << (8 * (i - 4));
+  }
+  if (layered) {
+    // Areas' code ranges are disjoint and every rank lies in one area, so
+    // each rank's code is its own LUT entry: clear, then one write per rank.
+    for (uint32_t c = threadIdx.x; c < 2048; c += blockDim.x) lut[c] = 0x8000;
+    lds_barrier();
+    for (uint32_t r = threadIdx.x; r < f; r += blockDim.x) {
+      uint32_t a = 0;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) a += ((uint32_t)k < na && A.first[k] <= r) ? 1u : 0u;
+      uint32_t wa = A.w[0], oa = A.off[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        wa = a == (uint32_t)k ? A.w[k] : wa;
+        oa = a == (uint32_t)k ? A.off[k] : oa;
+      }
+      const uint32_t suffix = r - oa;
+      if (suffix < (1u << wa)) lut[(a << wa) + suffix] = table->rank_to_sym[r];
     }
+  } else {
+    // Any other table: per entry, the last area whose range holds the code
+    // and whose rank is valid.
     for (uint32_t c = threadIdx.x; c < 2048; c += blockDim.x) {
       uint32_t e = 0x8000;
 #pragma unroll
       for (int a = 0; a < 8; ++a) {
-        if (c >= lo[a] && c < lo[a] + (1u << w[a])) {
-          const uint32_t rank = off[a] + (c - lo[a]);
-          if (rank >= first[a] && rank < first[a] + cnt[a] && rank < 256)
+        if (c >= lo[a] && c < lo[a] + (1u << A.w[a])) {
+          const uint32_t rank = A.off[a] + (c - lo[a]);
+          if (rank >= A.first[a] && rank < A.first[a] + A.cnt[a] && rank < 256)
             e = table->rank_to_sym[rank];
         }
       }
@@ -1436,10 +1506,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
   __shared__ DecSmem S;
   const uint32_t tid = threadIdx.x;
   uint32_t sh_lo, sh_hi;
-  build_dec_lut(table, S.lut, sh_lo, sh_hi);
+  qlc_table* tl = (qlc_table*)S.ring;  // the ring is free until the decode starts
+  table_to_lds(table, tl, tid);
+  __syncthreads();
+  build_dec_lut(tl, S.lut, sh_lo, sh_hi);
+  const bool table_ok = mode_symbol_bits(tl->mode) == kBits;
   __syncthreads();
   // a table of another alphabet is refused (nothing decoded)
-  if (mode_symbol_bits(table->mode) == kBits) {
+  if (table_ok) {
     const bool bad = decode_block<kBits>(bits, *total_p, index, log2_chunk, n, out, blockIdx.x,
                                          sh_lo, sh_hi, S, tid);
     set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
@@ -1449,6 +1523,384 @@ __global__ __launch_bounds__(kDecThreads) void k_decode(
 
   // ---- error word: first error wins; the last workgroup publishes it ----
   __syncthreads();
+  if (tid == 0) {
+    const uint32_t done = atomic_add_u32(&hdr->dec_done, 1u);
+    if (done == gridDim.x - 1) {
+      *err_out = load_relaxed_u32(&hdr->dec_err);
+      store_relaxed_u32(&hdr->dec_err, 0);
+      store_relaxed_u32(&hdr->dec_done, 0);
+    }
+  }
+}
+
+// ===========================================================================
+// Split-chunk decode: several lanes per chunk.
+//
+// With one lane per chunk (k_decode) a tensor of few chunks leaves the
+// device idle: a 1 Mi-symbol tensor at C = 2048 is 512 chunks, i.e. 512
+// lanes, each walking 2048 codes one after the other.  Here a workgroup
+// takes kSplitSyms (16384) symbols, i.e. 16384 / C whole chunks, and gives
+// every chunk G = C / 64 lanes (C <= 16384), about 64 codes per lane:
+//   1. the workgroup's stretch of the bitstream is copied into LDS with
+//      coalesced 16-byte loads (each stream byte is read once);
+//   2. lane g of a chunk takes the g-th of G equal pieces of the chunk's
+//      bits and walks code lengths only (a code's length follows from its
+//      area code alone), starting kSplitWarmBits before its piece as if a
+//      code began there (a guess; exact for g = 0).  Walks of a prefix code
+//      from a wrong start soon fall onto the true boundaries, so the walk
+//      usually enters the piece in step with them.  The lane owns the codes
+//      that start in its piece; it records where its walk enters and leaves
+//      the piece and how many codes it passed in between;
+//   3. correction rounds: a lane whose start differs from the point where
+//      the previous lane's walk left the previous piece walks again from
+//      that point, in step with its old path, until the two paths meet
+//      (from there on they coincide) or the piece ends.  After round r the
+//      first r + 1 lanes of every chunk are exact; the rounds stop when no
+//      lane's exit changed, so after at most G + 1 rounds, and in practice
+//      the two paths meet within a few codes and one round suffices;
+//   4. a scan of the code counts gives every lane the position of its first
+//      symbol; the lane decodes its codes through the code-word LUT into an
+//      LDS copy of the workgroup's output, which is then stored with
+//      coalesced stores.
+// If every code length is a multiple of d (the gcd of the lengths of the
+// areas in use), code starts lie d apart from the chunk's start and the
+// guesses are rounded to that grid: a table whose codes all have one length
+// needs no correction at all.  A chunk is reported corrupt under the same
+// conditions as in k_decode: its codes do not end exactly where the next
+// chunk begins (or at the stream's end) after its symbol count, a suffix
+// lies outside its area, or its index entries are out of order.
+// ===========================================================================
+constexpr int kSplitThreads = 256;
+constexpr uint32_t kSplitLog2Syms = kSplitMaxLog2Chunk;      // symbols per workgroup
+constexpr uint32_t kSplitSyms = 1u << kSplitLog2Syms;
+constexpr uint32_t kMaxCodeBits = 11;                         // 3-bit area code + 8-bit suffix
+constexpr uint32_t kSplitCapBits = kSplitSyms * kMaxCodeBits + 128;  // + alignment of the base
+constexpr uint32_t kSplitPadWords = 4;                        // zero words before the stream copy
+constexpr uint32_t kSplitLoadWords = ((kSplitCapBits + 31) / 32 + 4 + 3) & ~3u;
+constexpr uint32_t kSplitSpanWords = kSplitPadWords + kSplitLoadWords;
+constexpr uint32_t kSplitLoadsPerLane = (kSplitLoadWords / 4 + kSplitThreads - 1) / kSplitThreads;
+constexpr uint32_t kSplitQOff = kSplitPadWords * 32 - 1;      // LDS bit of stream bit 0, minus one
+constexpr uint32_t kSplitMaxChunks = kSplitSyms >> 8;         // chunks per workgroup at C = 256
+constexpr uint32_t kSplitWarmBits = 384;                      // walked before a piece, not counted
+
+struct SplitSmem {
+  uint32_t lut[2048];
+  uint32_t span[kSplitSpanWords];         // stream words from base_bit on (memory byte order)
+  uint8_t out[kSplitSyms];                // decoded symbols, one per byte
+  uint32_t xs[2][kSplitThreads];          // walk exits, by round parity
+  uint32_t excl[kSplitThreads];           // exclusive scan of the code counts
+  uint32_t wsum[kSplitThreads / 64];
+  uint32_t chunk_bad[kSplitMaxChunks];
+  uint32_t any[3];                        // correction rounds: some exit changed
+};
+
+static_assert(offsetof(SplitSmem, span) % 16 == 0 && offsetof(SplitSmem, out) % 16 == 0,
+              "16-byte LDS accesses");
+static_assert(sizeof(SplitSmem) * 3 <= 160 * 1024, "three workgroups per CU");
+
+// Length of the code starting at stream bit `rel` (relative to the copy).
+__device__ __forceinline__ uint32_t split_code_len(const uint32_t* span, uint32_t rel,
+                                                   uint32_t sh_lo, uint32_t sh_hi) {
+  const uint32_t q = rel + kSplitQOff;
+  const uint32_t w0 = __builtin_bswap32(span[q >> 5]), w1 = __builtin_bswap32(span[(q >> 5) + 1]);
+  const uint32_t A = __builtin_amdgcn_alignbit(w0, w1, ~q);
+  const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
+  return 32u - __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
+}
+
+// The four words holding stream bits rel .. rel + 95 (and q for the chain).
+__device__ __forceinline__ Window split_window(const uint32_t* span, uint32_t rel, uint32_t& q) {
+  q = rel + kSplitQOff;
+  const uint32_t* rr = span + (q >> 5);
+  Window w;
+  w.w0 = rr[0];
+  w.w1 = rr[1];
+  w.w2 = rr[2];
+  w.w3 = rr[3];
+  return w;
+}
+
+// Walk code lengths from x while x < end: returns the first code start at
+// or past end and adds the codes passed to cnt.
+__device__ __forceinline__ uint32_t split_walk(const uint32_t* span, uint32_t x, uint32_t end,
+                                               uint32_t sh_lo, uint32_t sh_hi, uint32_t& cnt) {
+  while (x < end) {
+    uint32_t q;
+    const Window W = split_window(span, x, q);
+    const uint32_t w0 = __builtin_bswap32(W.w0), w1 = __builtin_bswap32(W.w1);
+    const uint32_t w2 = __builtin_bswap32(W.w2), w3 = __builtin_bswap32(W.w3);
+    uint32_t A = __builtin_amdgcn_alignbit(w0, w1, ~q);
+    uint32_t B = __builtin_amdgcn_alignbit(w1, w2, ~q);
+    uint32_t Cw = __builtin_amdgcn_alignbit(w2, w3, ~q);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {  // at most 88 of the window's 96 bits
+      const uint32_t sel = __builtin_amdgcn_alignbit(kAreaSel, A, 29);
+      const uint32_t sft = __builtin_amdgcn_perm(sh_hi, sh_lo, sel);
+      const bool act = x < end;  // once past the end, x stays there
+      x += act ? 32u - sft : 0u;
+      cnt += act ? 1u : 0u;
+      A = __builtin_amdgcn_alignbit(A, B, sft);
+      B = __builtin_amdgcn_alignbit(B, Cw, sft);
+      Cw = __builtin_amdgcn_alignbit(Cw, 0u, sft);
+    }
+  }
+  return x;
+}
+
+// gcd of the code lengths of the areas that hold symbols: the largest k
+// that divides every length (lengths are at most kMaxCodeBits).
+__device__ __forceinline__ uint32_t code_length_gcd(const qlc_table* __restrict__ table) {
+  const AreaFields A = read_areas(table);
+  uint32_t lens = 0;  // bit L set: some area has codes of length L
+#pragma unroll
+  for (uint32_t a = 0; a < 8; ++a)
+    if (a < A.na && A.cnt[a] != 0) lens |= 1u << (A.p + A.w[a]);
+  uint32_t d = 1;
+#pragma unroll
+  for (uint32_t k = 2; k <= kMaxCodeBits; ++k) {
+    uint32_t mult = 0;
+#pragma unroll
+    for (uint32_t m = k; m <= kMaxCodeBits; m += k) mult |= 1u << m;
+    if (lens != 0 && (lens & ~mult) == 0) d = k;
+  }
+  return d;
+}
+
+template <int kBits>
+__global__ __launch_bounds__(kSplitThreads) void k_decode_split(
+    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
+    const uint64_t* __restrict__ index_p, uint32_t log2_chunk,
+    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out_p,
+    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
+  __shared__ SplitSmem S;
+  const QLC_GLOBAL uint64_t* __restrict__ index = (const QLC_GLOBAL uint64_t*)index_p;
+  const uint32_t tid = threadIdx.x;
+  // the table's copy goes to the output buffer (free until the decode); its
+  // load is issued first and written after the stream's loads
+  qlc_table* tl = (qlc_table*)S.out;
+  const bool tab_lane = tid < sizeof(qlc_table) / 16;
+  const uint4 tv = tab_lane ? ((const uint4*)table)[tid] : make_uint4(0, 0, 0, 0);
+  if (tid < kSplitPadWords) S.span[tid] = 0;
+  if (tid < 3) S.any[tid] = 0;
+  if (tid < kSplitMaxChunks) S.chunk_bad[tid] = 0;
+
+  const uint32_t C = 1u << log2_chunk;
+  const uint32_t log2_g = log2_chunk - 6;                 // G = C / 64 lanes per chunk
+  const uint32_t G = 1u << log2_g;
+  const uint32_t g = tid & (G - 1);
+  const uint32_t slot = tid >> log2_g;                    // chunk slot in the workgroup
+  const uint64_t nchunks = (n + C - 1) >> log2_chunk;
+  const uint64_t j0 = (uint64_t)blockIdx.x << (kSplitLog2Syms - log2_chunk);
+  const uint64_t j = j0 + slot;
+  const uint64_t total = *total_p;
+  // this lane's index entries, loaded with the span's
+  uint64_t s_abs = 0, e_abs = 0;
+  if (j < nchunks) {
+    s_abs = index[j];
+    e_abs = j + 1 < nchunks ? index[j + 1] : total;
+  }
+
+  // ---- the workgroup's stretch of the stream ----
+  uint64_t base_bit = 0, hi = 0;
+  if (j0 < nchunks) {
+    const uint64_t s0 = index[j0];
+    base_bit = (((s0 < total ? s0 : total) >> 3) & ~15ull) << 3;
+    const uint64_t jl = (j0 + (kSplitSyms >> log2_chunk) < nchunks ? j0 + (kSplitSyms >> log2_chunk)
+                                                                  : nchunks) - 1;
+    hi = jl + 1 < nchunks ? index[jl + 1] : total;
+    if (hi < base_bit) hi = base_bit;
+    if (hi - base_bit > kSplitCapBits) hi = base_bit + kSplitCapBits;
+  }
+  // the table's copy first, then the stream's loads, which stay in flight
+  // while the LUT is built
+  if (tab_lane) ((uint4*)tl)[tid] = tv;
+  const uint32_t nvec =
+      j0 < nchunks ? (uint32_t)((((hi - base_bit + 31) >> 5) + 4 + 3) >> 2) : 0u;
+  uint4 sv[kSplitLoadsPerLane];
+  {
+    const uint64_t stream_bytes = ((total + 31) >> 5) << 2;
+    const uint64_t base_byte = base_bit >> 3;
+    uint64_t avail = stream_bytes > base_byte ? stream_bytes - base_byte : 0;
+    if (avail > (1u << 20)) avail = 1u << 20;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(bits + (base_byte < stream_bytes ? base_byte : 0)), (short)0, (int)(uint32_t)avail,
+        0x00020000);
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitLoadsPerLane; ++k) {
+      const uint32_t i = tid + k * kSplitThreads;
+      sv[k] = bufload16(rsrc, i < nvec ? i * 16 : kOobOffset);
+    }
+  }
+  lds_barrier();
+  uint32_t sh_lo, sh_hi;
+  build_dec_lut(tl, S.lut, sh_lo, sh_hi);
+  const bool table_ok = mode_symbol_bits(tl->mode) == kBits;
+  const uint32_t d = code_length_gcd(tl);
+#pragma unroll
+  for (uint32_t k = 0; k < kSplitLoadsPerLane; ++k) {
+    const uint32_t i = tid + k * kSplitThreads;
+    if (i < nvec) *(uint4*)&S.span[kSplitPadWords + 4 * i] = sv[k];
+  }
+  lds_barrier();
+
+  // ---- this lane's chunk and piece ----
+  bool live = false;
+  uint32_t s_rel = 0, e_rel = 0, nsym = 0, lo = 0, piece_lo = 0, end = 0;
+  if (table_ok && j < nchunks) {
+    const uint64_t s = s_abs, e = e_abs;
+    const uint64_t left = n - (j << log2_chunk);
+    nsym = (uint32_t)(left < C ? left : C);
+    live = s <= e && e <= total && (j != 0 || s == 0) && s >= base_bit &&
+           e - base_bit <= kSplitCapBits && e - s <= (uint64_t)nsym * kMaxCodeBits;
+    if (live) {
+      s_rel = (uint32_t)(s - base_bit);
+      e_rel = (uint32_t)(e - base_bit);
+      const uint32_t len = e_rel - s_rel;
+      const uint32_t piece = (len + G - 1) >> log2_g;
+      const uint32_t a = min(g * piece, len), b = min((g + 1) * piece, len);
+      // the walk starts kSplitWarmBits before the piece (on the d grid of
+      // the chunk): by the piece's first bit it has most likely fallen in
+      // step with the true code boundaries
+      uint32_t u = a > kSplitWarmBits ? a - kSplitWarmBits : 0;
+      if (d > 1) u = (u + d - 1) / d * d;
+      lo = s_rel + u;
+      piece_lo = s_rel + a;
+      end = s_rel + b;
+    } else {
+      S.chunk_bad[slot] = 1;  // every lane of the chunk writes the same
+    }
+  }
+
+  // ---- phase 1: length walks from the guessed starts ----
+  uint32_t start = 0, cnt = 0, x = 0;
+  if (live) {
+    uint32_t warm = 0;
+    start = split_walk(S.span, lo, piece_lo, sh_lo, sh_hi, warm);  // first start in the piece
+    x = split_walk(S.span, start, end, sh_lo, sh_hi, cnt);
+  }
+
+  // ---- phase 2: correction rounds ----
+  S.xs[0][tid] = x;
+  lds_barrier();
+  for (uint32_t r = 0; r <= kSplitThreads; ++r) {
+    const uint32_t prev = g == 0 ? s_rel : S.xs[r & 1][tid - 1];
+    bool changed = false;
+    if (live && g != 0 && prev != start) {
+      // new path from prev, old path from start, in step until they meet
+      uint32_t a = prev, b = start, ca = 0, cb = 0;
+      bool met = false;
+      for (;;) {
+        if (a == b) {
+          met = true;
+          break;
+        }
+        if (a < b) {
+          if (a >= end) break;
+          a += split_code_len(S.span, a, sh_lo, sh_hi);
+          ++ca;
+        } else {
+          if (b >= end) break;
+          b += split_code_len(S.span, b, sh_lo, sh_hi);
+          ++cb;
+        }
+      }
+      const uint32_t nx = met ? x : a;
+      cnt = met ? cnt - cb + ca : ca;
+      changed = nx != x;
+      x = nx;
+      start = prev;
+    }
+    // any lane changed?  (three flag words: the one read after this
+    // round's barrier is cleared two rounds later)
+    if (tid == 0) S.any[(r + 1) % 3] = 0;
+    if (changed) S.any[r % 3] = 1;
+    S.xs[(r + 1) & 1][tid] = x;
+    lds_barrier();
+    if (!S.any[r % 3]) break;
+  }
+
+  // ---- phase 3: first symbol of each lane (scan of the counts) ----
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) {
+    const uint32_t y = __shfl_up(incl, k, 64);
+    if (lane >= (uint32_t)k) incl += y;
+  }
+  if (lane == 63) S.wsum[wave] = incl;
+  lds_barrier();
+  for (uint32_t w = 0; w < wave; ++w) incl += S.wsum[w];
+  S.excl[tid] = incl - cnt;
+  lds_barrier();
+  const uint32_t cbase = S.excl[tid - g];
+  if (live && g == G - 1 && (incl - cbase != nsym || x != e_rel)) S.chunk_bad[slot] = 1;
+  lds_barrier();
+  bool bad = table_ok && j < nchunks && S.chunk_bad[slot] != 0;
+
+  // ---- phase 4: decode into the LDS copy of the output ----
+  if (live && !bad) {
+    uint8_t* dst = S.out + (slot << log2_chunk) + (incl - cnt - cbase);
+    uint32_t pos = start, errbits = 0, q;
+    Window W = split_window(S.span, pos, q);
+    const uint32_t full = cnt >> 3, rem = cnt & 7u;
+    for (uint32_t k0 = 0; k0 < full; ++k0, dst += 8) {
+      uint32_t e[8];
+      pos += decode_chain(W, q, sh_lo, sh_hi, S.lut, e);
+      W = split_window(S.span, pos, q);  // the next group's window, read early
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) {
+        dst[k] = (uint8_t)e[k];
+        errbits |= e[k];
+      }
+    }
+    if (rem) {
+      uint32_t e[8];
+      decode_chain(W, q, sh_lo, sh_hi, S.lut, e);
+#pragma unroll
+      for (uint32_t k = 0; k < 7; ++k) {
+        if (k < rem) {
+          dst[k] = (uint8_t)e[k];
+          errbits |= e[k];
+        }
+      }
+    }
+    bad = (errbits & 0x8000u) != 0;
+  }
+  set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
+  if (!table_ok && tid == 0) set_error(&hdr->dec_err, QLC_ERR_INVALID_ARGUMENT);
+  lds_barrier();
+
+  // ---- the workgroup's output, coalesced ----
+  const uint64_t sym0 = (uint64_t)blockIdx.x << kSplitLog2Syms;
+  if (table_ok && sym0 < n) {
+    const uint32_t nsw = (uint32_t)(n - sym0 < kSplitSyms ? n - sym0 : kSplitSyms);
+    QLC_GLOBAL uint8_t* o = (QLC_GLOBAL uint8_t*)out_p + ((sym0 * kBits) >> 3);
+    if (kBits == 8) {
+      for (uint32_t i = tid; i < (nsw >> 4); i += kSplitThreads) {
+        const uint4 v = *(const uint4*)&S.out[16 * i];
+        GVec4 w;
+        w.x = v.x;
+        w.y = v.y;
+        w.z = v.z;
+        w.w = v.w;
+        ((QLC_GLOBAL GVec4*)o)[i] = w;
+      }
+      for (uint32_t i = (nsw & ~15u) + tid; i < nsw; i += kSplitThreads) o[i] = S.out[i];
+    } else {
+      for (uint32_t i = tid; i < (nsw >> 3); i += kSplitThreads)
+        store_group<kBits>(o + i * kBits, pack_out<kBits>(*(const uint2*)&S.out[8 * i]));
+      const uint32_t rem = nsw & 7u;
+      if (rem && tid == 0) {  // whole bytes; the last one zero padded
+        uint64_t acc = 0;
+        for (uint32_t k = 0; k < rem; ++k)
+          acc |= (uint64_t)S.out[(nsw & ~7u) + k] << (k * kBits);
+        QLC_GLOBAL uint8_t* t = o + (nsw >> 3) * kBits;
+        for (uint32_t b = 0; b < (rem * kBits + 7) / 8; ++b) t[b] = (uint8_t)(acc >> (8 * b));
+      }
+    }
+  }
+
+  // ---- error word: first error wins; the last workgroup publishes it ----
   if (tid == 0) {
     const uint32_t done = atomic_add_u32(&hdr->dec_done, 1u);
     if (done == gridDim.x - 1) {
@@ -1747,8 +2199,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     const uint32_t k = __builtin_amdgcn_readfirstlane(grp_job[p]);
     const qlc_job jb = jobs[k];
     if (k != cur) {
-      build_dec_lut(jb.table, S.lut, sh_lo, sh_hi);
-      tab_ok = mode_symbol_bits(jb.table->mode) == kBits;
+      qlc_table* tl = (qlc_table*)S.ring;  // free between work items
+      table_to_lds(jb.table, tl, tid);
+      __syncthreads();
+      build_dec_lut(tl, S.lut, sh_lo, sh_hi);
+      tab_ok = mode_symbol_bits(tl->mode) == kBits;
       __syncthreads();
       cur = k;
     }
@@ -1834,6 +2289,18 @@ hipError_t launch_decode(const uint8_t* bits_in, const uint64_t* total, const ui
   if (blocks < 1) blocks = 1;
   QLC_LAUNCH_BITS(bits, k_decode, dim3((uint32_t)blocks), dim3(kDecThreads), bits_in, total,
                   index, log2_chunk, table, n, out, err_out, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_split(const uint8_t* bits_in, const uint64_t* total, const uint64_t* index,
+                               uint32_t log2_chunk, const qlc_table* table, uint64_t n,
+                               uint32_t bits, uint8_t* out, uint32_t* err_out, WsHeader* hdr,
+                               hipStream_t stream) {
+  if (log2_chunk < 8 || log2_chunk > kSplitMaxLog2Chunk) return hipErrorInvalidValue;
+  uint64_t blocks = (n + kSplitSyms - 1) >> kSplitLog2Syms;
+  if (blocks < 1) blocks = 1;
+  QLC_LAUNCH_BITS(bits, k_decode_split, dim3((uint32_t)blocks), dim3(kSplitThreads), bits_in,
+                  total, index, log2_chunk, table, n, out, err_out, hdr);
   return hipGetLastError();
 }
 

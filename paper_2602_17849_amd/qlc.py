@@ -39,6 +39,13 @@ LAYOUT_M64_AREAS4 = 50
 LAYOUT_M64_AREAS8 = 51
 
 
+# decoder choice of qlc_decode_ex
+DECODER_AUTO = 0
+DECODER_LANE = 1
+DECODER_SPLIT = 2
+SPLIT_MAX_CHUNK = 16384
+
+
 def mode_symbol_bits(mode: int) -> int:
     """Bits per symbol of the alphabet a layout mode codes."""
     return 4 if mode in (48, 49) else 6 if mode in (50, 51) else 8
@@ -146,6 +153,9 @@ _SIGNATURES = {
                        ctypes.c_int),
     "qlc_decode_sym": ([_vp, _vp, _vp, _u32, _vp, _u64, _u32, _vp, _vp, _vp, _sz, _vp],
                        ctypes.c_int),
+    "qlc_decoder_choice": ([_u64, _u32], ctypes.c_int),
+    "qlc_decode_ex": ([_vp, _vp, _vp, _u32, _vp, _u64, _u32, ctypes.c_int, _vp, _vp, _vp, _sz,
+                       _vp], ctypes.c_int),
     "qlc_encode_batched_sym": ([_vp, _u32, _u32, ctypes.c_int, _u32, _vp, _vp, _sz, _vp],
                                ctypes.c_int),
     "qlc_decode_batched_sym": ([_vp, _u32, _u32, _u32, _vp, _vp, _sz, _vp], ctypes.c_int),
@@ -351,6 +361,19 @@ def qlc_decode_sym(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor,
                                 _stream(stream)), "qlc_decode_sym")
 
 
+def qlc_decoder_choice(n: int, chunk_symbols: int) -> int:
+    """The decoder DECODER_AUTO takes for n symbols at chunk size C."""
+    return int(lib().qlc_decoder_choice(n, chunk_symbols))
+
+
+def qlc_decode_ex(bits: torch.Tensor, total: torch.Tensor, index: torch.Tensor,
+                  chunk_symbols: int, table: torch.Tensor, n: int, symbol_bits: int, decoder: int,
+                  out: torch.Tensor, err_out: torch.Tensor, ws: torch.Tensor, stream=None):
+    _check(lib().qlc_decode_ex(_p(bits), _p(total), _p(index), chunk_symbols, _p(table), n,
+                               symbol_bits, decoder, _p(out), _p(err_out), _p(ws), _nbytes(ws),
+                               _stream(stream)), "qlc_decode_ex")
+
+
 def qlc_encode_batched_sym(jobs: torch.Tensor, n_jobs: int, symbol_bits: int, mode: int,
                            chunk_symbols: int, ws: torch.Tensor, tuning=None, stream=None):
     keep, tp = _tuning_ptr(tuning)
@@ -470,12 +493,14 @@ def compress(x: torch.Tensor, mode: int = LAYOUT_SEARCH_QUAD, chunk_symbols: int
     return Compressed(n, chunk_symbols, table, bits, index, total, err)
 
 
-def decompress(c: Compressed, out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+def decompress(c: Compressed, out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+               decoder: int = DECODER_AUTO):
     dev = c.bits.device
     out = torch.empty(max(c.n, 16), dtype=torch.uint8, device=dev)[:c.n] if out is None else out
     err = torch.empty(1, dtype=torch.int32, device=dev)
     ws = new_workspace(0, c.chunk_symbols, dev) if ws is None else ws
-    qlc_decode(c.bits, c.total, c.index, c.chunk_symbols, c.table, c.n, out, err, ws)
+    qlc_decode_ex(c.bits, c.total, c.index, c.chunk_symbols, c.table, c.n, 8, decoder, out, err,
+                  ws)
     return out, err
 
 

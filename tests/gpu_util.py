@@ -59,13 +59,20 @@ def gpu_encode(x_dev, t_dev, C, cap=None):
             index[:qlc.qlc_chunk_count(n, C)].cpu().numpy().astype(np.uint64), tb)
 
 
-def gpu_decode(bits_np, total, index_np, C, t_dev, n):
+def gpu_decode(bits_np, total, index_np, C, t_dev, n, decoder=None, symbol_bits=8):
+    """Decode through qlc_decode (decoder None) or qlc_decode_ex with the
+    given decoder; returns (err, output bytes)."""
     bits = to_dev(np.concatenate([bits_np, np.zeros(16, np.uint8)]))
     tot = torch.tensor([total], dtype=torch.int64, device=DEV)
     idx = to_dev(index_np.astype(np.int64)) if index_np.size else torch.zeros(1, dtype=torch.int64, device=DEV)
-    out = torch.full((max(n, 16),), 0xAA, dtype=torch.uint8, device=DEV)
+    nb = qlc.packed_bytes(n, symbol_bits)
+    out = torch.full((max(nb, 16),), 0xAA, dtype=torch.uint8, device=DEV)
     err = torch.full((1,), -1, dtype=torch.int32, device=DEV)
     ws = qlc.new_workspace(0, C)
-    qlc.qlc_decode(bits, tot, idx, C, t_dev, n, out, err, ws)
+    if decoder is None and symbol_bits == 8:
+        qlc.qlc_decode(bits, tot, idx, C, t_dev, n, out, err, ws)
+    else:
+        qlc.qlc_decode_ex(bits, tot, idx, C, t_dev, n, symbol_bits,
+                          qlc.DECODER_AUTO if decoder is None else decoder, out, err, ws)
     torch.cuda.synchronize()
-    return int(err.item()), out[:n].cpu().numpy()
+    return int(err.item()), out[:nb].cpu().numpy()

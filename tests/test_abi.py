@@ -67,6 +67,15 @@ def test_argument_errors_are_synchronous():
     assert L.qlc_histogram_accumulate(ws, 1 << 20, ws, ws, 16, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_decode(ws, 0, ws, 4096, ws, 10, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_encode(ws, 1 << 36, ws, 4096, ws, 64, ws, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    # decoder choice: unknown decoder, split decoder above C = 16384, bad symbol width
+    assert L.qlc_decode_ex(ws, ws, ws, 4096, ws, 10, 8, 3, ws, ws, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    for C in (32768, 65536):
+        assert L.qlc_decode_ex(ws, ws, ws, C, ws, 10, 8, qlc.DECODER_SPLIT, ws, ws, ws, big,
+                               0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_decode_ex(ws, ws, ws, 4096, ws, 10, 5, qlc.DECODER_SPLIT, ws, ws, ws, big,
+                           0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    assert L.qlc_decode_ex(ws, ws, ws, 4096, ws, 10, 8, qlc.DECODER_SPLIT, ws + 8, ws, ws, big,
+                           0) == qlc.QLC_ERR_INVALID_ARGUMENT
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -208,3 +217,20 @@ def test_host_table_deserialize_small_alphabets(M, A, p):
         bad[i], bad[j] = bad[j], bad[i]
         with pytest.raises(qlc.QLCError):
             qlc.qlc_table_deserialize(bytes(bad))
+
+
+def test_decoder_choice():
+    """QLC_DECODER_AUTO's rule: the shorter of two fitted time models (lane:
+    max(14.6 us + 36.7 ns * C, 0.615 ps * n); split: 25 us + 1.28 ps * n,
+    C <= 16384), checked at the measured points it was fitted to."""
+    ch = qlc.qlc_decoder_choice
+    L, S = qlc.DECODER_LANE, qlc.DECODER_SPLIT
+    assert ch(1 << 20, 256) == L and ch(1 << 22, 256) == L        # short chunks: lanes suffice
+    assert ch(1 << 20, 2048) == S and ch(9437184, 2048) == S and ch(1 << 24, 2048) == S
+    assert ch(1 << 26, 2048) == L and ch(1 << 28, 2048) == L      # enough chunks to fill
+    assert ch(1 << 26, 4096) == S and ch(1 << 28, 4096) == L
+    assert ch(1 << 28, 16384) == S
+    assert ch(1 << 20, 32768) == L and ch(1 << 20, 65536) == L    # split needs C <= 16384
+    assert ch(0, 2048) in (L, S)
+    assert ch(1 << 20, 100) == qlc.DECODER_AUTO
+

@@ -79,9 +79,10 @@ def test_fullsize_sampled_chunks_match_oracle(compressed):
     assert not tail.any()
 
 
-def test_fullsize_round_trip(compressed):
+@pytest.mark.parametrize("decoder", [qlc.DECODER_AUTO, qlc.DECODER_LANE, qlc.DECODER_SPLIT])
+def test_fullsize_round_trip(compressed, decoder):
     x, obj = compressed
-    out, err = qlc.decompress(obj)
+    out, err = qlc.decompress(obj, decoder=decoder)
     torch.cuda.synchronize()
     assert int(err.item()) == 0
     assert torch.equal(out, x)

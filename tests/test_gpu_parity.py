@@ -230,15 +230,22 @@ def test_encode_bit_exact(n, C):
             assert np.array_equal(index, oindex), (name, mode)
 
 
+DECODERS = [qlc.DECODER_LANE, qlc.DECODER_SPLIT]
+
+
+@pytest.mark.parametrize("decoder", DECODERS)
 @pytest.mark.parametrize("C", [256, 1024, 4096, 65536])
 @pytest.mark.parametrize("n", SIZES)
-def test_decode_oracle_streams(n, C):
-    """Decode streams written by the oracle (independent of the GPU encoder)."""
+def test_decode_oracle_streams(n, C, decoder):
+    """Decode streams written by the oracle (independent of the GPU encoder),
+    with either decoder (the split one takes C <= 16384)."""
+    if decoder == qlc.DECODER_SPLIT and C > qlc.SPLIT_MAX_CHUNK:
+        pytest.skip("split decoder: C <= 16384")
     for name, x in _inputs(n, seed=3):
         for mode in (0, 1, 2, 3):
             ot = oracle.build_table(oracle.histogram(x), mode)
             st, obits, oindex, ototal = oracle.encode(x, ot, C)
-            err, out = gpu_decode(obits, ototal, oindex, C, table_from_oracle(ot), n)
+            err, out = gpu_decode(obits, ototal, oindex, C, table_from_oracle(ot), n, decoder)
             assert err == 0, (name, mode)
             assert np.array_equal(out, x), (name, mode)
 
@@ -252,7 +259,8 @@ def test_round_trip_gpu_only():
     assert torch.equal(out, x)
 
 
-def test_decode_error_codes_match_oracle():
+@pytest.mark.parametrize("decoder", DECODERS)
+def test_decode_error_codes_match_oracle(decoder):
     rng = np.random.default_rng(4)
     x = rng.integers(0, 256, 20000).astype(np.uint8)
     C = 256
@@ -270,7 +278,7 @@ def test_decode_error_codes_match_oracle():
         cases["flip%d" % k] = (b2, total, index, x.size)
     for name, (b, tb, idx, n) in cases.items():
         ost, oout = oracle.decode(b, tb, idx, C, ot, n)
-        err, out = gpu_decode(b, tb, idx, C, t, n)
+        err, out = gpu_decode(b, tb, idx, C, t, n, decoder)
         assert err == ost, name
         if ost == 0:
             assert np.array_equal(out, oout), name
