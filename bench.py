@@ -58,7 +58,10 @@ def load_profile(kernel: str) -> dict:
         return {}
     if rec.get("source_hash") != kernel_source_hash():
         return {}
-    return rec.get("kernels", {}).get(kernel) or {}
+    for name, v in rec.get("kernels", {}).items():  # names carry template arguments
+        if name.split("<")[0] == kernel:
+            return v
+    return {}
 
 
 def _host_cpu():

@@ -220,7 +220,7 @@ def collect_sq(chunk, kernel="k_decode"):
         per = {}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
-                if short(r["Kernel_Name"]) != kernel:
+                if short(r["Kernel_Name"]).split("<")[0] != kernel:
                     continue
                 key = (r["Counter_Name"], r["Dispatch_Id"])
                 per[key] = per.get(key, 0.0) + float(r["Counter_Value"])

@@ -1212,7 +1212,10 @@ __device__ __forceinline__ void build_dec_lut(const qlc_table* __restrict__ tabl
   layered = layered && f <= 256;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const uint32_t sft = 32u - p - A.w[i >> (3 - p)];
+    // area named by top bits i: i >> (3 - p), selected without indexing
+    // the array by a run-time value (which would put it in scratch memory)
+    const uint32_t wi = p == 3 ? A.w[i] : p == 2 ? A.w[i >> 1] : A.w[i >> 2];
+    const uint32_t sft = 32u - p - wi;
     if (i < 4) sh_lo |= sft << (8 * i);
     else sh_hi |= sft << (8 * (i - 4));
   }
