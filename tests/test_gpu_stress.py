@@ -69,6 +69,17 @@ def test_stress_4gib(kind):
     index = b.chunk_index(0).cpu().numpy()
     _check_sampled_chunks(b, 0, xh, ot, index, total)
 
+    # the split decoder on the same stream: bit offsets past 2^32, 2^18
+    # workgroups (under SEARCH_QUAD the uniform stream's codes all have one
+    # length, so its guessed starts are exact; the others need corrections)
+    b.out.zero_()
+    derr = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    qlc.qlc_decode_ex(b.bitstream(0), b.total[0:1], b.chunk_index(0), C, b.table(0), N, 8,
+                      qlc.DECODER_SPLIT, b.output(0), derr, qlc.new_workspace(0, C, DEV))
+    torch.cuda.synchronize()
+    assert int(derr.item()) == 0
+    assert torch.equal(b.output(0), x), "split decoder round trip"
+
     if kind == "uniform":
         # Table 1's layout expands incompressible data (8 -> ~9.59 bits)
         del b
