@@ -468,7 +468,8 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 30):
+def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 30,
+                decoder=None):
     """The serving loop (qlc_server_*) under Poisson arrivals, then the same
     requests submitted at once (saturation)."""
     import torch
@@ -508,7 +509,8 @@ def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 3
     out = {}
     for mode in ("poisson", "saturation"):
         srv = qlc.Server(budget, chunk_symbols=chunk, max_jobs_per_tick=64,
-                         max_ticks_in_flight=4, log2_segment=log2_segment)
+                         max_ticks_in_flight=4, log2_segment=log2_segment,
+                         decoder=qlc.DECODER_AUTO if decoder is None else decoder)
         lat, done_bytes, last, pending = [], [0], [0], {}
         t0 = time.perf_counter_ns()
         for i, (t_arr, kind, n) in enumerate(reqs):
@@ -535,6 +537,7 @@ def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 3
             "peak_bytes_in_use": int(st.peak_bytes_in_use)}
         print("serving %s: %s" % (mode, out[mode]), file=sys.stderr, flush=True)
     return {"workload": SERVE_WORKLOAD, "chunk_symbols": chunk, "log2_segment": log2_segment,
+            "decoder": ["auto", "lane", "split"][qlc.DECODER_AUTO if decoder is None else decoder],
             "budget_bytes": budget, "latency": "scheduled arrival to completion seen by the "
             "server thread", **out}
 

@@ -353,7 +353,12 @@ typedef struct qlc_batch_tuning {
                             encode items, raised to the largest job's segment
                             count (0: every histogram first) */
   uint32_t workgroups;   /* persistent workgroups (0: fill the device)        */
-  uint32_t reserved;     /* 0 */
+  uint32_t decoder;      /* decode: QLC_DECODER_AUTO (0) = jobs of fewer than
+                            256 chunks in split units of 2^14 symbols (C/64
+                            lanes per chunk, C <= 16384), the others one lane
+                            per chunk; QLC_DECODER_LANE = every job one lane
+                            per chunk; QLC_DECODER_SPLIT = every job split
+                            (C <= 16384).  Ignored by encode.               */
 } qlc_batch_tuning;
 
 /* Workspace bytes for batched calls over n_jobs jobs holding at most

@@ -55,7 +55,8 @@ typedef struct qlc_server_config {
   uint32_t max_jobs_per_tick;   /* 0: 256                                     */
   uint32_t max_ticks_in_flight; /* streams / tick slots, 0: 2 (at most 8)     */
   uint32_t log2_segment;        /* batched work split (0: library default)    */
-  uint32_t reserved;            /* 0 */
+  uint32_t decoder;             /* qlc_batch_tuning.decoder of the decode
+                                   ticks (0: QLC_DECODER_AUTO)                */
 } qlc_server_config;
 
 typedef enum qlc_request_kind {

@@ -100,12 +100,17 @@ BatchView carve_batch(void* ws, size_t ws_bytes, uint32_t n_jobs, bool decode) {
   return v;
 }
 
-bool batch_tuning(const qlc_batch_tuning* t, uint32_t* log2_seg, uint32_t* lag, uint32_t* wgs) {
+bool batch_tuning(const qlc_batch_tuning* t, uint32_t* log2_seg, uint32_t* lag, uint32_t* wgs,
+                  uint32_t* decoder = nullptr) {
   *log2_seg = kBatchDefaultLog2Seg;
   *lag = 0;
   *wgs = 0;
+  if (decoder) *decoder = QLC_DECODER_AUTO;
   if (!t) return true;
-  if (t->reserved) return false;
+  if (t->decoder != QLC_DECODER_AUTO && t->decoder != QLC_DECODER_LANE &&
+      t->decoder != QLC_DECODER_SPLIT)
+    return false;
+  if (decoder) *decoder = t->decoder;
   if (t->log2_segment) {
     if (t->log2_segment < kBatchMinLog2Seg || t->log2_segment > kBatchMaxLog2Seg) return false;
     *log2_seg = t->log2_segment;
@@ -425,7 +430,11 @@ size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint
   if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return 0;
   const uint64_t segs = (total_symbols >> log2_seg) + n_jobs;
-  const uint64_t groups = (total_symbols >> (log2c + kDecThreadsLog2)) + n_jobs;
+  // decode units: lane groups of kDecThreads chunks (2^16 symbols or more)
+  // or split units of 2^14 symbols, whichever each job gets: at most one
+  // split unit per 2^14 symbols plus one per job
+  static_assert(kDecThreadsLog2 + 8 >= kSplitUnitLog2, "split units outnumber lane groups");
+  const uint64_t groups = (total_symbols >> kSplitUnitLog2) + n_jobs;
   const uint64_t enc = segs * kBatchSegBytes, dec = groups * kBatchGroupBytes;
   return round256(batch_units_offset(n_jobs) + (enc > dec ? enc : dec));
 }
@@ -442,7 +451,7 @@ qlc_status qlc_encode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t
   if (n_jobs == 0) return QLC_OK;
   if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
   BatchView v = carve_batch(ws, ws_bytes, n_jobs, false);
-  hipError_t e = launch_batch_plan(jobs, n_jobs, false, log2_seg, v.max_units, lag, v.hdr, v.js,
+  hipError_t e = launch_batch_plan(jobs, n_jobs, false, 0, log2_seg, v.max_units, lag, v.hdr, v.js,
                                    v.job_hist, v.unit_job, v.seg_word, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
   return hip_status(launch_encode_batched(jobs, symbol_bits, (uint32_t)mode, log2_seg, log2c,
@@ -460,16 +469,22 @@ qlc_status qlc_encode_batched(const qlc_job* jobs, uint32_t n_jobs, qlc_layout_m
 qlc_status qlc_decode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t symbol_bits,
                                   uint32_t chunk_symbols, const qlc_batch_tuning* h_tuning,
                                   void* ws, size_t ws_bytes, hipStream_t stream) {
-  uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
+  uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0, decoder = 0;
   if (!valid_chunk(chunk_symbols, &log2c) || !valid_symbol_bits(symbol_bits) ||
-      !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
+      !batch_tuning(h_tuning, &log2_seg, &lag, &wgs, &decoder))
     return QLC_ERR_INVALID_ARGUMENT;
+  if (decoder == QLC_DECODER_SPLIT && log2c > kSplitMaxLog2Chunk) return QLC_ERR_INVALID_ARGUMENT;
   if ((n_jobs && !jobs) || !ws || !aligned(jobs, 8) || !aligned(ws, 256)) return QLC_ERR_INVALID_ARGUMENT;
   if (n_jobs == 0) return QLC_OK;
   if (ws_bytes < batch_units_offset(n_jobs)) return QLC_ERR_INVALID_ARGUMENT;
   BatchView v = carve_batch(ws, ws_bytes, n_jobs, true);
-  hipError_t e = launch_batch_plan(jobs, n_jobs, true, log2c + kDecThreadsLog2, v.max_units, 0, v.hdr, v.js,
-                                   v.job_hist, v.unit_job, nullptr, stream);
+  // split units: every job (SPLIT), or (AUTO) jobs of fewer chunks than a
+  // lane group holds, whose lanes would otherwise idle
+  const uint32_t split = decoder == QLC_DECODER_SPLIT ? 2u
+                         : decoder == QLC_DECODER_AUTO && log2c <= kSplitMaxLog2Chunk ? 1u
+                                                                                       : 0u;
+  hipError_t e = launch_batch_plan(jobs, n_jobs, true, split, log2c + kDecThreadsLog2, v.max_units,
+                                   0, v.hdr, v.js, v.job_hist, v.unit_job, nullptr, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
   return hip_status(launch_decode_batched(jobs, symbol_bits, log2c, v.hdr, v.js, v.unit_job,
                                           persistent_grid(true, wgs), stream));

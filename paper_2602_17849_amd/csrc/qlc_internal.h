@@ -119,7 +119,10 @@ static_assert(sizeof(BatchHeader) == 256, "batch header size");
 struct BatchJobState {
   uint32_t base;         // first unit of the job
   uint32_t count;        // units of the job (0: job skipped)
-  uint32_t hist_done;    // encode: histogram items finished
+  union {
+    uint32_t hist_done;  // encode: histogram items finished
+    uint32_t split;      // decode: 1 = split units of 2^14 symbols
+  };
   uint32_t table_ready;  // encode: all histograms in (and the table built)
 };
 

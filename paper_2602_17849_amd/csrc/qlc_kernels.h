@@ -28,14 +28,17 @@ hipError_t launch_decode(const uint8_t* bits_in, const uint64_t* total, const ui
                          uint8_t* out, uint32_t* err_out, WsHeader* hdr, hipStream_t stream);
 // Several lanes per chunk (log2_chunk <= kSplitMaxLog2Chunk).
 constexpr uint32_t kSplitMaxLog2Chunk = 14;
+constexpr uint32_t kSplitUnitLog2 = 14;  // symbols per split unit (one workgroup)
 hipError_t launch_decode_split(const uint8_t* bits_in, const uint64_t* total, const uint64_t* index,
                                uint32_t log2_chunk, const qlc_table* table, uint64_t n,
                                uint32_t bits, uint8_t* out, uint32_t* err_out, WsHeader* hdr,
                                hipStream_t stream);
-hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
-                             uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
-                             uint64_t* job_hist, uint32_t* unit_job, uint64_t* seg_word,
-                             hipStream_t stream);
+// decode_split (decode only): 0 every job one lane per chunk, 1 jobs of
+// fewer than kDecThreads chunks in split units, 2 every job in split units.
+hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode,
+                             uint32_t decode_split, uint32_t log2_unit, uint64_t max_units,
+                             uint32_t lag, BatchHeader* hdr, BatchJobState* js, uint64_t* job_hist,
+                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream);
 hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t bits, uint32_t mode,
                                  uint32_t log2_seg, uint32_t log2_chunk, BatchHeader* hdr,
                                  BatchJobState* js, uint64_t* job_hist, const uint32_t* seg_job,

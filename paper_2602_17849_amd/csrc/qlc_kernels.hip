@@ -1669,19 +1669,32 @@ __device__ __forceinline__ uint32_t code_length_gcd(const qlc_table* __restrict_
   return d;
 }
 
+// The LUT of a split decode and what the walks need from the table.
+struct SplitLut {
+  uint32_t sh_lo, sh_hi;  // shift table (see build_dec_lut)
+  uint32_t d;             // gcd of the code lengths in use
+  bool ok;                // the table codes this alphabet
+};
+
+// Decode split unit `unit` (symbols unit * 16384 onwards) of an n-symbol
+// stream with all 256 threads of the block (tid = threadIdx.x).  With
+// `table` given, the LUT is built into S.lut and L set (while the stream's
+// loads are in flight); with table == nullptr, S.lut and L hold a LUT built
+// before.  Stores the unit's symbols; returns true in the lanes of a corrupt
+// chunk.  Nothing is decoded or stored if L.ok is false.
 template <int kBits>
-__global__ __launch_bounds__(kSplitThreads) void k_decode_split(
-    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
-    const uint64_t* __restrict__ index_p, uint32_t log2_chunk,
-    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out_p,
-    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
-  __shared__ SplitSmem S;
+__device__ __forceinline__ bool split_block(const uint8_t* __restrict__ bits, uint64_t total,
+                                            const uint64_t* __restrict__ index_p,
+                                            uint32_t log2_chunk, uint64_t n,
+                                            uint8_t* __restrict__ out_p, uint64_t unit,
+                                            const qlc_table* __restrict__ table, SplitLut& L,
+                                            SplitSmem& S, uint32_t tid) {
   const QLC_GLOBAL uint64_t* __restrict__ index = (const QLC_GLOBAL uint64_t*)index_p;
-  const uint32_t tid = threadIdx.x;
-  // the table's copy goes to the output buffer (free until the decode); its
-  // load is issued first and written after the stream's loads
+  // a table to build the LUT from: its copy goes to the output buffer
+  // (free until the decode); its load is issued first and written after the
+  // stream's loads
   qlc_table* tl = (qlc_table*)S.out;
-  const bool tab_lane = tid < sizeof(qlc_table) / 16;
+  const bool tab_lane = table != nullptr && tid < sizeof(qlc_table) / 16;
   const uint4 tv = tab_lane ? ((const uint4*)table)[tid] : make_uint4(0, 0, 0, 0);
   if (tid < kSplitPadWords) S.span[tid] = 0;
   if (tid < 3) S.any[tid] = 0;
@@ -1693,9 +1706,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_decode_split(
   const uint32_t g = tid & (G - 1);
   const uint32_t slot = tid >> log2_g;                    // chunk slot in the workgroup
   const uint64_t nchunks = (n + C - 1) >> log2_chunk;
-  const uint64_t j0 = (uint64_t)blockIdx.x << (kSplitLog2Syms - log2_chunk);
+  const uint64_t j0 = unit << (kSplitLog2Syms - log2_chunk);
   const uint64_t j = j0 + slot;
-  const uint64_t total = *total_p;
   // this lane's index entries, loaded with the span's
   uint64_t s_abs = 0, e_abs = 0;
   if (j < nchunks) {
@@ -1735,10 +1747,13 @@ __global__ __launch_bounds__(kSplitThreads) void k_decode_split(
     }
   }
   lds_barrier();
-  uint32_t sh_lo, sh_hi;
-  build_dec_lut(tl, S.lut, sh_lo, sh_hi);
-  const bool table_ok = mode_symbol_bits(tl->mode) == kBits;
-  const uint32_t d = code_length_gcd(tl);
+  if (table != nullptr) {
+    build_dec_lut(tl, S.lut, L.sh_lo, L.sh_hi);
+    L.ok = mode_symbol_bits(tl->mode) == kBits;
+    L.d = code_length_gcd(tl);
+  }
+  const uint32_t sh_lo = L.sh_lo, sh_hi = L.sh_hi, d = L.d;
+  const bool table_ok = L.ok;
 #pragma unroll
   for (uint32_t k = 0; k < kSplitLoadsPerLane; ++k) {
     const uint32_t i = tid + k * kSplitThreads;
@@ -1869,12 +1884,10 @@ __global__ __launch_bounds__(kSplitThreads) void k_decode_split(
     }
     bad = (errbits & 0x8000u) != 0;
   }
-  set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
-  if (!table_ok && tid == 0) set_error(&hdr->dec_err, QLC_ERR_INVALID_ARGUMENT);
   lds_barrier();
 
   // ---- the workgroup's output, coalesced ----
-  const uint64_t sym0 = (uint64_t)blockIdx.x << kSplitLog2Syms;
+  const uint64_t sym0 = unit << kSplitLog2Syms;
   if (table_ok && sym0 < n) {
     const uint32_t nsw = (uint32_t)(n - sym0 < kSplitSyms ? n - sym0 : kSplitSyms);
     QLC_GLOBAL uint8_t* o = (QLC_GLOBAL uint8_t*)out_p + ((sym0 * kBits) >> 3);
@@ -1902,6 +1915,24 @@ __global__ __launch_bounds__(kSplitThreads) void k_decode_split(
       }
     }
   }
+
+  return bad;
+}
+
+template <int kBits>
+__global__ __launch_bounds__(kSplitThreads) void k_decode_split(
+    const uint8_t* __restrict__ bits, const uint64_t* __restrict__ total_p,
+    const uint64_t* __restrict__ index_p, uint32_t log2_chunk,
+    const qlc_table* __restrict__ table, uint64_t n, uint8_t* __restrict__ out_p,
+    uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr) {
+  __shared__ SplitSmem S;
+  const uint32_t tid = threadIdx.x;
+  SplitLut L;
+  const bool bad = split_block<kBits>(bits, *total_p, index_p, log2_chunk, n, out_p, blockIdx.x,
+                                      table, L, S, tid);
+  set_error_wave(&hdr->dec_err, QLC_ERR_CORRUPT_STREAM, bad);
+  if (!L.ok && tid == 0) set_error(&hdr->dec_err, QLC_ERR_INVALID_ARGUMENT);
+  lds_barrier();
 
   // ---- error word: first error wins; the last workgroup publishes it ----
   if (tid == 0) {
@@ -1964,7 +1995,8 @@ constexpr uint32_t kPlanZeroJobs = 16;  // job histograms cleared per extra plan
 // Workgroup 0 plans; workgroups 1.. (encode only) clear the per-job
 // histogram accumulators, kPlanZeroJobs jobs each.
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
-    const qlc_job* __restrict__ jobs, uint32_t n_jobs, uint32_t decode, uint32_t log2_unit,
+    const qlc_job* __restrict__ jobs, uint32_t n_jobs, uint32_t decode, uint32_t decode_split,
+    uint32_t log2_unit,
     uint64_t max_units, uint32_t lag_req, BatchHeader* __restrict__ hdr,
     BatchJobState* __restrict__ js, uint64_t* __restrict__ job_hist,
     uint32_t* __restrict__ unit_job, uint64_t* __restrict__ seg_word) {
@@ -1988,10 +2020,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
   uint32_t maxc = 0;
   for (uint32_t k = k0; k < k1; ++k) {
     const qlc_job jb = jobs[k];
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, split = 0;
     if (jb.err && ptr_aligned(jb.err, 4)) {
       if (job_valid(jb, decode != 0)) {
-        const uint64_t u = (jb.n + (1ull << log2_unit) - 1) >> log2_unit;
+        // decode: a job of fewer chunks than one lane group fills goes to
+        // split units (decode_split = 1), or every job (2); log2_unit is
+        // log2 C + kDecThreadsLog2 (a lane group of kDecThreads chunks)
+        const uint32_t l2c = log2_unit - kDecThreadsLog2;
+        const uint64_t chunks = (jb.n + (1ull << l2c) - 1) >> l2c;
+        split = decode && (decode_split == 2 || (decode_split == 1 && chunks < kDecThreads));
+        const uint32_t lu = split ? kSplitLog2Syms : log2_unit;
+        const uint64_t u = (jb.n + (1ull << lu) - 1) >> lu;
         cnt = (uint32_t)(decode ? u : (u ? u : 1));
         *jb.err = 0;
       } else {
@@ -1999,8 +2038,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
       }
     }
     js[k].count = cnt;
-    js[k].hist_done = 0;
+    js[k].hist_done = 0;  // decode: js[k].split (the same word)
     js[k].table_ready = 0;
+    if (decode) js[k].split = split;
     local += cnt;
     maxc = cnt > maxc ? cnt : maxc;
   }
@@ -2184,16 +2224,27 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
   }
 }
 
+// Work items of a batched decode: a group of kDecThreads chunks decoded one
+// lane per chunk, or, for jobs the plan marked split, a split unit of
+// kSplitSyms symbols (split_block).  Both layouts start with the LUT, which
+// is rebuilt only when the job changes.
+union BatchDecSmem {
+  DecSmem lane;
+  SplitSmem split;
+};
+static_assert(offsetof(DecSmem, lut) == 0 && offsetof(SplitSmem, lut) == 0, "shared LUT");
+static_assert(kSplitThreads == kDecThreads, "one block size");
+
 template <int kBits>
 __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     const qlc_job* __restrict__ jobs, uint32_t log2_chunk, BatchHeader* __restrict__ hdr,
     const BatchJobState* __restrict__ js, const uint32_t* __restrict__ grp_job) {
-  __shared__ DecSmem S;
+  __shared__ BatchDecSmem S;
   __shared__ uint32_t s_ticket;
   const uint32_t tid = threadIdx.x;
   const uint32_t units = hdr->units;
-  uint32_t cur = ~0u, sh_lo = 0, sh_hi = 0;
-  bool tab_ok = false;
+  uint32_t cur = ~0u;
+  SplitLut L{0, 0, 1, false};
   for (;;) {
     if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
     __syncthreads();
@@ -2202,18 +2253,23 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
     const uint32_t k = __builtin_amdgcn_readfirstlane(grp_job[p]);
     const qlc_job jb = jobs[k];
     if (k != cur) {
-      qlc_table* tl = (qlc_table*)S.ring;  // free between work items
+      qlc_table* tl = (qlc_table*)S.lane.ring;  // free between work items
       table_to_lds(jb.table, tl, tid);
       __syncthreads();
-      build_dec_lut(tl, S.lut, sh_lo, sh_hi);
-      tab_ok = mode_symbol_bits(tl->mode) == kBits;
+      build_dec_lut(tl, S.lane.lut, L.sh_lo, L.sh_hi);
+      L.ok = mode_symbol_bits(tl->mode) == kBits;
+      L.d = code_length_gcd(tl);
       __syncthreads();
       cur = k;
     }
-    if (tab_ok) {
-      const bool bad = decode_block<kBits>(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk,
-                                           jb.n, jb.out, p - js[k].base, sh_lo, sh_hi, S,
-                                           opaque_tid());
+    if (L.ok) {
+      const uint32_t unit = p - js[k].base;
+      const bool bad =
+          __builtin_amdgcn_readfirstlane(js[k].split)
+              ? split_block<kBits>(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk, jb.n,
+                                   jb.out, unit, nullptr, L, S.split, opaque_tid())
+              : decode_block<kBits>(jb.bits, *jb.total_bits, jb.chunk_index, log2_chunk, jb.n,
+                                    jb.out, unit, L.sh_lo, L.sh_hi, S.lane, opaque_tid());
       set_error_wave(jb.err, QLC_ERR_CORRUPT_STREAM, bad);
     } else if (tid == 0) {
       set_error(jb.err, QLC_ERR_INVALID_ARGUMENT);  // a table of another alphabet
@@ -2307,14 +2363,14 @@ hipError_t launch_decode_split(const uint8_t* bits_in, const uint64_t* total, co
   return hipGetLastError();
 }
 
-hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode, uint32_t log2_unit,
-                             uint64_t max_units, uint32_t lag, BatchHeader* hdr, BatchJobState* js,
-                             uint64_t* job_hist, uint32_t* unit_job, uint64_t* seg_word,
-                             hipStream_t stream) {
+hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode,
+                             uint32_t decode_split, uint32_t log2_unit, uint64_t max_units,
+                             uint32_t lag, BatchHeader* hdr, BatchJobState* js, uint64_t* job_hist,
+                             uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream) {
   const uint32_t grid = 1 + (decode ? 0u : (n_jobs + kPlanZeroJobs - 1) / kPlanZeroJobs);
   hipLaunchKernelGGL(k_batch_plan, dim3(grid), dim3(kPlanThreads), 0, stream, jobs, n_jobs,
-                     decode ? 1u : 0u, log2_unit, max_units, lag, hdr, js, job_hist, unit_job,
-                     seg_word);
+                     decode ? 1u : 0u, decode_split, log2_unit, max_units, lag, hdr, js,
+                     job_hist, unit_job, seg_word);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 #include "qlc.h"
 #include "qlc_server.h"
 #include "qlc_internal.h"
+#include "qlc_kernels.h"
 
 namespace qlc {
 namespace {
@@ -333,7 +334,10 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
   if (c.memory_budget_bytes == 0 || C < QLC_MIN_CHUNK || C > QLC_MAX_CHUNK || (C & (C - 1)) ||
       !valid_layout_mode(c.layout_mode) || mode_symbol_bits(c.layout_mode) != 8 ||
       c.max_jobs_per_tick > kMaxJobs ||
-      c.max_ticks_in_flight > kMaxTicks || c.reserved ||
+      c.max_ticks_in_flight > kMaxTicks ||
+      (c.decoder != QLC_DECODER_AUTO && c.decoder != QLC_DECODER_LANE &&
+       c.decoder != QLC_DECODER_SPLIT) ||
+      (c.decoder == QLC_DECODER_SPLIT && C > (1u << kSplitMaxLog2Chunk)) ||
       (c.log2_segment && (c.log2_segment < 13 || c.log2_segment > 24)))
     return QLC_ERR_INVALID_ARGUMENT;
   if (!c.max_jobs_per_tick) c.max_jobs_per_tick = kDefaultJobs;
@@ -344,7 +348,7 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
   qlc_server* s = new (std::nothrow) qlc_server();
   if (!s) return QLC_ERR_HIP;
   s->cfg = c;
-  s->tuning = qlc_batch_tuning{c.log2_segment, 0, 0, 0};
+  s->tuning = qlc_batch_tuning{c.log2_segment, 0, 0, c.decoder};
   bool ok = hipGetDevice(&s->device) == hipSuccess &&
             hipMalloc((void**)&s->pool_base, c.memory_budget_bytes) == hipSuccess;
   s->pool.init(c.memory_budget_bytes);

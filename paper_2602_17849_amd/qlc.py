@@ -119,7 +119,7 @@ class BatchTuning(ctypes.Structure):
         ("log2_segment", ctypes.c_uint32),
         ("lag_segments", ctypes.c_uint32),
         ("workgroups", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("decoder", ctypes.c_uint32),   # decode: DECODER_AUTO / _LANE / _SPLIT
     ]
 
 _lib = None
@@ -621,7 +621,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("memory_budget_bytes", ctypes.c_uint64), ("max_tick_symbols", ctypes.c_uint64),
                 ("chunk_symbols", ctypes.c_uint32), ("layout_mode", ctypes.c_uint32),
                 ("max_jobs_per_tick", ctypes.c_uint32), ("max_ticks_in_flight", ctypes.c_uint32),
-                ("log2_segment", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("log2_segment", ctypes.c_uint32), ("decoder", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -692,10 +692,11 @@ class Server:
 
     def __init__(self, memory_budget_bytes: int, chunk_symbols: int = 4096,
                  layout_mode: int = LAYOUT_SEARCH_QUAD, max_jobs_per_tick: int = 0,
-                 max_ticks_in_flight: int = 0, log2_segment: int = 0, max_tick_symbols: int = 0):
+                 max_ticks_in_flight: int = 0, log2_segment: int = 0, max_tick_symbols: int = 0,
+                 decoder: int = DECODER_AUTO):
         lib()
         cfg = ServerConfig(memory_budget_bytes, max_tick_symbols, chunk_symbols, layout_mode,
-                           max_jobs_per_tick, max_ticks_in_flight, log2_segment, 0)
+                           max_jobs_per_tick, max_ticks_in_flight, log2_segment, decoder)
         h = ctypes.c_void_p()
         _check(_lib.qlc_server_create(ctypes.addressof(cfg), ctypes.byref(h)), "qlc_server_create")
         self._h = h

@@ -131,7 +131,8 @@ def test_batched_workspace_query():
     assert f(3, 0, 4096) > 0
     assert f(1, 1 << 20, 1000) == 0                         # C not a power of two
     assert f(1, 1 << 20, 4096, (12, 0, 0, 0)) == 0          # segment below 2^13
-    assert f(1, 1 << 20, 4096, (13, 0, 0, 1)) == 0          # reserved field set
+    assert f(1, 1 << 20, 4096, (13, 0, 0, 3)) == 0          # unknown decoder
+    assert f(1, 1 << 20, 4096, (13, 0, 0, qlc.DECODER_SPLIT)) > 0
 
 
 def test_batched_argument_errors_are_synchronous():
@@ -149,6 +150,10 @@ def test_batched_argument_errors_are_synchronous():
     assert L.qlc_encode_batched(ws, 4, 0, 4096, None, ws, 256, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_decode_batched(ws, 4, 4096 * 32, None, ws, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_decode_batched(ws, 4, 4096, None, 0, big, 0) == qlc.QLC_ERR_INVALID_ARGUMENT
+    for dec, C in ((3, 4096), (qlc.DECODER_SPLIT, 32768)):   # unknown decoder; split above 16384
+        tun = qlc.BatchTuning(0, 0, 0, dec)
+        assert L.qlc_decode_batched(ws, 4, C, ctypes.addressof(tun), ws, big, 0) == \
+            qlc.QLC_ERR_INVALID_ARGUMENT
     assert L.qlc_encode_batched(0, 0, 0, 4096, None, ws, big, 0) == qlc.QLC_OK   # no jobs
 
 
@@ -160,7 +165,8 @@ def test_server_config_errors_are_synchronous():
            qlc.ServerConfig(1 << 20, 0, 4096, 7, 0, 0, 0, 0),       # unknown layout mode
            qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 9, 0, 0),       # too many ticks in flight
            qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 0, 30, 0),      # segment out of range
-           qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 0, 0, 1)]       # reserved field set
+           qlc.ServerConfig(1 << 20, 0, 4096, 0, 0, 0, 0, 3),       # unknown decoder
+           qlc.ServerConfig(1 << 20, 0, 32768, 0, 0, 0, 0, qlc.DECODER_SPLIT)]  # split, C > 16384
     for cfg in bad:
         assert L.qlc_server_create(ctypes.addressof(cfg), ctypes.byref(h)) == \
             qlc.QLC_ERR_INVALID_ARGUMENT

@@ -272,6 +272,40 @@ def test_batched_errors_stay_per_job():
         assert np.array_equal(b.output(i).cpu().numpy(), xs[i]), i
 
 
+@pytest.mark.parametrize("decoder", [qlc.DECODER_LANE, qlc.DECODER_SPLIT, qlc.DECODER_AUTO])
+@pytest.mark.parametrize("C", [256, 4096, 16384])
+def test_batched_decoders_round_trip(decoder, C):
+    """Every job decoded one lane per chunk, in split units, or (automatic)
+    split for jobs of fewer than 256 chunks: the same bytes back."""
+    b, xs = make_batch(SIZES, C, capacity="bound")    # Table 2 expands uniform bytes
+    tuning = (0, 0, 0, decoder)
+    ws = b.workspace(tuning)
+    b.encode(ws, qlc.LAYOUT_PAPER_T2, tuning)
+    torch.cuda.synchronize()
+    assert not b.err.any().item()
+    b.out.zero_()
+    b.decode(ws, tuning)
+    torch.cuda.synchronize()
+    check_round_trip(b, xs)
+
+
+@pytest.mark.parametrize("decoder", [qlc.DECODER_SPLIT, qlc.DECODER_AUTO])
+def test_batched_split_errors_stay_per_job(decoder):
+    C = 512
+    sizes = [300000, 70001, 40000, 5000, 262145]
+    b, xs = make_batch(sizes, C)
+    ws = b.workspace((0, 0, 0, decoder))
+    b.encode(ws, 0)
+    torch.cuda.synchronize()
+    assert b.err.cpu().numpy().tolist() == [0] * 5
+    b.chunk_index(2)[3] += 1                  # job 2 (78 chunks): split units under both
+    b.decode(ws, (0, 0, 0, decoder))
+    torch.cuda.synchronize()
+    assert b.err.cpu().numpy().tolist() == [0, 0, qlc.QLC_ERR_CORRUPT_STREAM, 0, 0]
+    for i in (0, 1, 3, 4):
+        assert np.array_equal(b.output(i).cpu().numpy(), xs[i]), i
+
+
 def test_batched_workspace_too_small():
     C = 4096
     sizes = [300000, 300001, 5000]

@@ -240,7 +240,8 @@ class _PackedBatch:
         return self.tables[i * qlc.TABLE_BYTES:(i + 1) * qlc.TABLE_BYTES]
 
 
-@pytest.mark.parametrize("tuning", [None, (13, 0, 0, 0), (14, 3, 5, 0)])
+@pytest.mark.parametrize("tuning", [None, (13, 0, 0, 0), (14, 3, 5, 0),
+                                    (0, 0, 0, qlc.DECODER_LANE), (0, 0, 0, qlc.DECODER_SPLIT)])
 @pytest.mark.parametrize("mode,M,A,p,bits", MODES, ids=MODE_IDS)
 def test_batched_sym(mode, M, A, p, bits, tuning):
     C = 1024
