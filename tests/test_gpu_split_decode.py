@@ -160,3 +160,24 @@ def test_split_rejects_large_chunks_and_unknown_decoders():
     st, bits, index, total = oracle.encode(x, ot, 256)
     with pytest.raises(qlc.QLCError):
         gpu_decode(bits, total, index, 256, t, n, 7)
+
+
+def test_split_refuses_a_table_of_another_alphabet():
+    """A byte stream decoded with a 16-symbol table (and the reverse) is
+    refused: QLC_ERR_INVALID_ARGUMENT, nothing written."""
+    n, C = 40000, 512
+    x = np.resize(datagen.gaussian(40000, 9).numpy(), n)
+    ot = oracle.build_table(oracle.histogram(x), qlc.LAYOUT_SEARCH_QUAD)
+    st, bits, index, total = oracle.encode(x, ot, C)
+    codes = datagen.small_float_codes(n, 1, 2, 9)
+    o16 = oracle.build_table_general(oracle.histogram(codes)[:16], 16, 4, 2, 4)
+    w = list(o16.width) + [0xFF] * 4
+    r2s = list(o16.rank_to_sym) + list(range(16, 256))
+    t16 = torch.frombuffer(bytearray(qlc.qlc_table_deserialize(bytes(w) + bytes(r2s))),
+                           dtype=torch.uint8).to(DEV)
+    assert qlc.mode_symbol_bits(int(qlc.parse_table(t16)["mode"])) == 4
+    for t, sb in ((t16, 8), (table_from_oracle(ot), 4)):
+        err, out = gpu_decode(bits, total, index, C, t, n, SPLIT, symbol_bits=sb)
+        assert err == qlc.QLC_ERR_INVALID_ARGUMENT, sb
+        assert (out == 0xAA).all(), sb
+
