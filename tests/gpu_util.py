@@ -23,8 +23,12 @@ def gpu_table(x_dev, mode):
 
 
 def table_from_oracle(ot) -> torch.Tensor:
-    """Device table holding the oracle table's layout (width + rank order)."""
-    blob = bytes(ot.width.astype(np.uint8)) + bytes(ot.rank_to_sym.astype(np.uint8))
+    """Device table holding the oracle table's layout (width + rank order);
+    a table of fewer areas or symbols is padded as the serialized form
+    requires (widths 0xFF, ranks beyond M in symbol order)."""
+    w = list(ot.width.astype(np.uint8)) + [0xFF] * (8 - len(ot.width))
+    r = list(ot.rank_to_sym.astype(np.uint8)) + list(range(len(ot.rank_to_sym), 256))
+    blob = bytes(w) + bytes(r)
     raw = qlc.qlc_table_deserialize(blob)
     return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(DEV)
 

@@ -170,14 +170,53 @@ def test_split_refuses_a_table_of_another_alphabet():
     ot = oracle.build_table(oracle.histogram(x), qlc.LAYOUT_SEARCH_QUAD)
     st, bits, index, total = oracle.encode(x, ot, C)
     codes = datagen.small_float_codes(n, 1, 2, 9)
-    o16 = oracle.build_table_general(oracle.histogram(codes)[:16], 16, 4, 2, 4)
-    w = list(o16.width) + [0xFF] * 4
-    r2s = list(o16.rank_to_sym) + list(range(16, 256))
-    t16 = torch.frombuffer(bytearray(qlc.qlc_table_deserialize(bytes(w) + bytes(r2s))),
-                           dtype=torch.uint8).to(DEV)
+    t16 = table_from_oracle(oracle.build_table_general(oracle.histogram(codes)[:16], 16, 4, 2, 4))
     assert qlc.mode_symbol_bits(int(qlc.parse_table(t16)["mode"])) == 4
     for t, sb in ((t16, 8), (table_from_oracle(ot), 4)):
         err, out = gpu_decode(bits, total, index, C, t, n, SPLIT, symbol_bits=sb)
         assert err == qlc.QLC_ERR_INVALID_ARGUMENT, sb
         assert (out == 0xAA).all(), sb
 
+
+
+def _random_case(rng):
+    n = int(np.exp(rng.uniform(0, np.log(1 << 21))))
+    C = int(2 ** rng.integers(8, 15))
+    kind = rng.integers(0, 5)
+    if kind == 0:
+        x = np.resize(datagen.gaussian(((n + 31) // 32) * 32, int(rng.integers(1 << 30))).numpy(), n)
+    elif kind == 1:
+        x = rng.integers(0, 256, n).astype(np.uint8)
+        x[rng.random(n) < rng.uniform(0.5, 0.999)] = 0
+    elif kind == 2:                      # long runs of one byte with bursts of others
+        x = np.full(n, rng.integers(0, 256), np.uint8)
+        for _ in range(int(rng.integers(0, 20))):
+            a = int(rng.integers(0, n)); b = min(n, a + int(rng.integers(1, 5000)))
+            x[a:b] = rng.integers(0, 256, b - a)
+    elif kind == 3:
+        x = rng.integers(0, 256, n).astype(np.uint8)
+    else:                                # a few symbols only
+        x = rng.choice(rng.integers(0, 256, int(rng.integers(1, 6))), n).astype(np.uint8)
+    mode = [0, 2, 3, 0, "d1", "d2", "d3", "a4"][int(rng.integers(0, 8))]
+    return n, C, x, mode
+
+
+def test_split_random_cases_match_oracle():
+    """60 seeded random cases (sizes 1..2 Mi, C 256..16384, skewed, uniform,
+    run-heavy and few-symbol data, several layouts): the split decoder
+    returns the oracle stream's input."""
+    rng = np.random.default_rng(2024)
+    for case in range(60):
+        n, C, x, mode = _random_case(rng)
+        h = oracle.histogram(x)
+        if mode == "a4":
+            ot = oracle.build_table_general(h, 256, 4, 2, 4)
+        elif isinstance(mode, str):
+            ot = oracle.build_table_general(h, 256, 8, 3, int(mode[1]))
+        else:
+            ot = oracle.build_table(h, mode)
+        st, bits, index, total = oracle.encode(x, ot, C)
+        assert st == 0
+        err, out = gpu_decode(bits, total, index, C, table_from_oracle(ot), n, SPLIT)
+        assert err == 0, (case, n, C, mode)
+        assert np.array_equal(out, x), (case, n, C, mode)
