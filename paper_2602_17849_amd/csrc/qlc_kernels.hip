@@ -143,6 +143,7 @@ static_assert(make_small_candidates<64, 8, kNumCandM64A8>().count == kNumCandM64
 struct TableSmem {
   uint64_t h[256];
   uint64_t key[256];        // count << 8 | (255 - symbol): unique sort keys
+  __attribute__((aligned(16))) uint32_t key32[256];  // the same while counts < 2^24
   uint64_t P[257];          // P[r] = sum of the counts of ranks < r
   uint64_t wave_min[16];
   uint32_t wave_pk[16];     // layout of each wave's cheapest candidate
@@ -166,15 +167,19 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   // (their counts must be zero) and keep ranks M..255 in symbol order
   const uint32_t sbits = mode_symbol_bits(mode);
   const uint32_t M = 1u << sbits;
-  int big = 0;  // a count of 2^48 or more, or a count of a symbol outside the alphabet
+  int big = 0;   // a count of 2^48 or more, or a count of a symbol outside the alphabet
+  int wide = 0;  // a count of 2^24 or more: the keys need 64 bits
   for (int s = tid; s < 256; s += nt) {
     uint64_t c = h_in[s];
     big |= ((c >> 48) != 0 || ((uint32_t)s >= M && c != 0)) ? 1 : 0;
     if ((uint32_t)s >= M) c = 0;
+    wide |= (c >> 24) != 0 ? 1 : 0;
     S.h[s] = c;
     S.key[s] = (c << 8) | (uint64_t)(255 - s);
+    S.key32[s] = (uint32_t)(c << 8) | (uint32_t)(255 - s);
   }
-  big = __syncthreads_or(big);
+  big = __syncthreads_or(big);  // (returns whether any thread's value is non-zero)
+  wide = __syncthreads_or(wide);
 
   // Rank = number of symbols that sort before s: larger count, or equal
   // count and smaller symbol value, i.e. the number of larger keys (counts
@@ -187,10 +192,21 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     const int span = 256 / parts;
     for (int i = tid; i < 256 * parts; i += nt) {
       const int s = i & 255, p = i >> 8;
-      const uint64_t ks = S.key[s];
       uint32_t r = 0;
+      if (!wide) {  // counts below 2^24: 32-bit keys, four per LDS read
+        const uint32_t ks = S.key32[s];
+        const uint4* kk = reinterpret_cast<const uint4*>(&S.key32[p * span]);
+#pragma unroll 8
+        for (int u = 0; u < span / 4; ++u) {
+          const uint4 v = kk[u];
+          r += (v.x > ks ? 1u : 0u) + (v.y > ks ? 1u : 0u) + (v.z > ks ? 1u : 0u) +
+               (v.w > ks ? 1u : 0u);
+        }
+      } else {
+        const uint64_t ks = S.key[s];
 #pragma unroll 16
-      for (int u = p * span; u < (p + 1) * span; ++u) r += S.key[u] > ks ? 1u : 0u;
+        for (int u = p * span; u < (p + 1) * span; ++u) r += S.key[u] > ks ? 1u : 0u;
+      }
       S.rpart[i] = r;
     }
     __syncthreads();
