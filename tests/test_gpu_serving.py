@@ -142,6 +142,19 @@ def test_many_requests_overlap(workload):
     assert all(v[0] == 0 for v in got.values())
 
 
+@pytest.mark.parametrize("decoder", [qlc.DECODER_LANE, qlc.DECODER_SPLIT])
+def test_decoders_of_the_decode_ticks(workload, decoder):
+    """Decompress requests decoded by lane groups only or split units only
+    return the original bytes."""
+    comp, dec_src, objs = workload
+    order = [("d", i) for i in range(len(dec_src))] * 2
+    with qlc.Server(256 << 20, chunk_symbols=C, max_jobs_per_tick=8, decoder=decoder) as srv:
+        ids = _submit_all(srv, comp, objs, order)
+        got = _collect(srv, ids)
+    for (kind, i), v in got.items():
+        assert v[0] == 0 and np.array_equal(v[1], dec_src[i].numpy()), (kind, i)
+
+
 def test_caller_table(workload):
     comp, _, _ = workload
     x = comp[5]
