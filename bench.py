@@ -468,7 +468,7 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=16, budget=32 << 30,
+def run_serving(dev, duration_s=10.0, chunk=512, log2_segment=0, budget=32 << 30,
                 decoder=None):
     """The serving loop (qlc_server_*) under Poisson arrivals, then the same
     requests submitted at once (saturation)."""

@@ -326,7 +326,7 @@ qlc_status qlc_decode_sym(const uint8_t* bits, const uint64_t* total_bits,
  * byte-identical to what the single-tensor entry points produce for it with
  * the same mode and C.  A call is a small planning kernel followed by one
  * persistent launch whose workgroups take work items (segment histograms,
- * table builds, segment encodes, or 128-chunk decode groups) from a shared
+ * table builds, segment encodes, 256-chunk decode groups or split units) from a shared
  * queue, so small shards do not leave the device idle.  Neither call
  * allocates, synchronises or sets memory from the host, so both may be
  * captured in a hipGraph and replayed. */
@@ -347,18 +347,25 @@ typedef struct qlc_job {
 
 /* Work split of a batched call; zero fields take the defaults. */
 typedef struct qlc_batch_tuning {
-  uint32_t log2_segment; /* encode work item = 2^log2_segment symbols, 13..24
-                            (default 18) */
+  uint32_t log2_segment; /* encode work item = 2^log2_segment symbols, 13..24;
+                            0: chosen on the device from T, the symbols of
+                            the call's valid jobs: floor(log2 T)/2 + 4
+                            clamped to 13..19 (about sqrt(T)/16 items) */
   uint32_t lag_segments; /* encode: histogram items handed out ahead of the
                             encode items, raised to the largest job's segment
                             count (0: every histogram first) */
   uint32_t workgroups;   /* persistent workgroups (0: fill the device)        */
-  uint32_t decoder;      /* decode: QLC_DECODER_AUTO (0) = jobs of fewer than
-                            256 chunks in split units of 2^14 symbols (C/64
-                            lanes per chunk, C <= 16384), the others one lane
-                            per chunk; QLC_DECODER_LANE = every job one lane
-                            per chunk; QLC_DECODER_SPLIT = every job split
-                            (C <= 16384).  Ignored by encode.               */
+  uint32_t decoder;      /* decode: QLC_DECODER_AUTO (0) = every job in split
+                            units of 2^14 symbols (C/64 lanes per chunk,
+                            C <= 16384) when a time model of the two
+                            decoders favours split for T symbols at this C
+                            (26 us + 2.5 ps/symbol against the larger of
+                            19.4 us + 44 ns * C and 0.46 ps/symbol), else
+                            only the jobs of fewer than 256 chunks, the
+                            others one lane per chunk; QLC_DECODER_LANE =
+                            every job one lane per chunk; QLC_DECODER_SPLIT =
+                            every job split (C <= 16384).  Ignored by
+                            encode.                                         */
 } qlc_batch_tuning;
 
 /* Workspace bytes for batched calls over n_jobs jobs holding at most

@@ -5,9 +5,11 @@
  *
  * Not a step of the paper: this is the deployment form around its codec.
  * Each request is one job of the batched entry points (qlc_encode_batched /
- * qlc_decode_batched), so its result is byte-identical to what the
- * single-tensor entry points give for it alone, whatever else shares its
- * tick.
+ * qlc_decode_batched), or, in a tick of one request, a call of the
+ * single-tensor entry points (qlc_compress / qlc_encode / qlc_decode_ex,
+ * whose fixed costs are lower for one tensor); either way its result is
+ * byte-identical to what the single-tensor entry points give for it alone,
+ * whatever else shares its tick.
  *
  * Model:
  *   - qlc_server_create reserves, once, a device pool of
@@ -26,7 +28,8 @@
  *   - A server thread admits queued requests in arrival order while they
  *     fit the budget and a tick slot is free, and launches them as one tick
  *     (batched encode for the compress jobs, batched decode for the
- *     decompress jobs) on the slot's stream; up to max_ticks_in_flight
+ *     decompress jobs; the single-tensor call for a tick of one request)
+ *     on the slot's stream; up to max_ticks_in_flight
  *     ticks overlap on the device, and requests arriving meanwhile join the
  *     next tick.  A request waiting for memory holds back those behind it
  *     (no overtaking).
@@ -54,7 +57,7 @@ typedef struct qlc_server_config {
   uint32_t layout_mode;         /* qlc_layout_mode of server-built tables     */
   uint32_t max_jobs_per_tick;   /* 0: 256                                     */
   uint32_t max_ticks_in_flight; /* streams / tick slots, 0: 2 (at most 8)     */
-  uint32_t log2_segment;        /* batched work split (0: library default)    */
+  uint32_t log2_segment;        /* batched work split (0: automatic, per tick) */
   uint32_t decoder;             /* qlc_batch_tuning.decoder of the decode
                                    ticks (0: QLC_DECODER_AUTO)                */
 } qlc_server_config;

@@ -102,7 +102,7 @@ BatchView carve_batch(void* ws, size_t ws_bytes, uint32_t n_jobs, bool decode) {
 
 bool batch_tuning(const qlc_batch_tuning* t, uint32_t* log2_seg, uint32_t* lag, uint32_t* wgs,
                   uint32_t* decoder = nullptr) {
-  *log2_seg = kBatchDefaultLog2Seg;
+  *log2_seg = 0;  // automatic (chosen by the plan kernel)
   *lag = 0;
   *wgs = 0;
   if (decoder) *decoder = QLC_DECODER_AUTO;
@@ -429,7 +429,8 @@ size_t qlc_batched_workspace_bytes(uint32_t n_jobs, uint64_t total_symbols, uint
   uint32_t log2c = 0, log2_seg = 0, lag = 0, wgs = 0;
   if (!valid_chunk(chunk_symbols, &log2c) || !batch_tuning(h_tuning, &log2_seg, &lag, &wgs))
     return 0;
-  const uint64_t segs = (total_symbols >> log2_seg) + n_jobs;
+  const uint64_t segs = log2_seg ? (total_symbols >> log2_seg) + n_jobs
+                                 : batch_auto_seg_bound(total_symbols, n_jobs);
   // decode units: lane groups of kDecThreads chunks (2^16 symbols or more)
   // or split units of 2^14 symbols, whichever each job gets: at most one
   // split unit per 2^14 symbols plus one per job
@@ -454,7 +455,7 @@ qlc_status qlc_encode_batched_sym(const qlc_job* jobs, uint32_t n_jobs, uint32_t
   hipError_t e = launch_batch_plan(jobs, n_jobs, false, 0, log2_seg, v.max_units, lag, v.hdr, v.js,
                                    v.job_hist, v.unit_job, v.seg_word, stream);
   if (e != hipSuccess) return QLC_ERR_HIP;
-  return hip_status(launch_encode_batched(jobs, symbol_bits, (uint32_t)mode, log2_seg, log2c,
+  return hip_status(launch_encode_batched(jobs, symbol_bits, (uint32_t)mode, log2c,
                                           v.hdr, v.js, v.job_hist, v.unit_job, v.seg_word,
                                           v.seg_hist, persistent_grid(false, wgs), stream));
 }

@@ -1,6 +1,7 @@
 // Internal layout shared by the libqlc host code and kernels (not installed).
 #pragma once
 
+#include <math.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -108,11 +109,12 @@ inline size_t ws_bytes_for(uint64_t n) {
 // Units are encode segments (seg_hist u32[256], seg_word u64, seg_job u32
 // each) or decode chunk groups (grp_job u32 each).
 struct BatchHeader {
-  uint32_t ticket;  // next work item of the persistent launch
-  uint32_t units;   // segments (encode) or chunk groups (decode) of all jobs
-  uint32_t lag;     // encode: histogram items handed out ahead of encode items
-  uint32_t abort;   // the plan found the workspace too small
-  uint32_t pad[60];
+  uint32_t ticket;    // next work item of the persistent launch
+  uint32_t units;     // segments (encode) or chunk groups (decode) of all jobs
+  uint32_t lag;       // encode: histogram items handed out ahead of encode items
+  uint32_t abort;     // the plan found the workspace too small
+  uint32_t log2_seg;  // encode: segment size the plan chose (or was given)
+  uint32_t pad[59];
 };
 static_assert(sizeof(BatchHeader) == 256, "batch header size");
 
@@ -126,9 +128,56 @@ struct BatchJobState {
   uint32_t table_ready;  // encode: all histograms in (and the table built)
 };
 
-constexpr uint32_t kBatchDefaultLog2Seg = 18;
 constexpr uint32_t kBatchMinLog2Seg = 13;
 constexpr uint32_t kBatchMaxLog2Seg = 24;
+constexpr uint32_t kBatchAutoMaxLog2Seg = 19;
+
+// Automatic work split of a batched call (tuning field 0), decided by the
+// plan kernel from T, the symbols of the call's valid jobs together.
+//
+// Encode: segments of 2^l symbols, l = floor(log2 T) / 2 + 4 clamped to
+// 13..19, i.e. about sqrt(T) / 16 segments.  An encode work item is one
+// workgroup streaming its segment tile after tile, so large segments leave
+// a small batch to a few workgroups (a 1 Mi-symbol job in 2^18-symbol
+// segments: four items, 106 us), and small ones multiply the predecessor
+// sums and table waits of a large batch; measured optima on MI355X: 2^13-14
+// up to 1 Mi symbols, 2^15 at 4 Mi, 2^16 at 16 Mi, 2^17 at 64 Mi.
+__host__ __device__ inline uint32_t batch_auto_log2_seg(uint64_t T) {
+  if (T == 0) return kBatchMinLog2Seg;
+  const uint32_t lg = 63u - (uint32_t)__builtin_clzll(T);
+  const uint32_t l = lg / 2 + 4;
+  return l < kBatchMinLog2Seg ? kBatchMinLog2Seg : l > kBatchAutoMaxLog2Seg ? kBatchAutoMaxLog2Seg : l;
+}
+
+// Decode (QLC_DECODER_AUTO): every job in split units when a time model of
+// the two decoders, fitted to batched decodes on MI355X, favours the split
+// one for T symbols at chunk size C = 2^log2c (C <= 16384): split about
+// 26 us + 2.5 ps per symbol (two workgroups of 256 lanes per CU on 2^14-
+// symbol units), one lane per chunk at least 19.4 us + 44 ns per code of a
+// chunk (a lane walks its chunk alone) and 0.46 ps per symbol once the
+// device is full.  Otherwise only jobs of fewer chunks than a lane group
+// holds are split.
+__host__ __device__ inline bool batch_split_all(uint64_t T, uint32_t log2c) {
+  if (log2c > 14 || T > (1ull << 40)) return false;
+  const uint64_t split_ns = 26000 + T * 25 / 10000;
+  const uint64_t lane_fill = 19400 + (44ull << log2c), lane_rate = T * 46 / 100000;
+  return split_ns < (lane_fill > lane_rate ? lane_fill : lane_rate);
+}
+
+// Segments a call of at most T symbols over n_jobs jobs can need under the
+// automatic encode split: sum_j ceil(n_j / 2^l) <= T' / 2^l(T') + n_jobs
+// for the T' <= T the plan sees, and T' / 2^l(T') is at most sqrt(T') / 8
+// (2^l >= 8 sqrt(T')), at most T' / 2^13, or T' / 2^19 where the cap holds.
+inline uint64_t batch_auto_seg_bound(uint64_t T, uint32_t n_jobs) {
+  if (T > (1ull << 62)) T = 1ull << 62;
+  uint64_t r = (uint64_t)sqrt((double)T);  // floor(sqrt(T)), corrected for rounding
+  while (r * r > T) --r;
+  while ((r + 1) * (r + 1) <= T) ++r;
+  const uint64_t by_root = r / 8 + 1, by_min = (T >> kBatchMinLog2Seg) + 1;
+  const uint64_t lo = by_root < by_min ? by_root : by_min;
+  const uint64_t by_cap = (T >> kBatchAutoMaxLog2Seg) + 1;
+  return (lo > by_cap ? lo : by_cap) + n_jobs;
+}
 constexpr size_t kBatchSegBytes = 256 * sizeof(uint32_t) + sizeof(uint64_t) + sizeof(uint32_t);
 constexpr size_t kBatchGroupBytes = sizeof(uint32_t);
 

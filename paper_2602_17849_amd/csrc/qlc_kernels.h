@@ -33,17 +33,20 @@ hipError_t launch_decode_split(const uint8_t* bits_in, const uint64_t* total, co
                                uint32_t log2_chunk, const qlc_table* table, uint64_t n,
                                uint32_t bits, uint8_t* out, uint32_t* err_out, WsHeader* hdr,
                                hipStream_t stream);
-// decode_split (decode only): 0 every job one lane per chunk, 1 jobs of
-// fewer than kDecThreads chunks in split units, 2 every job in split units.
+// log2_unit: encode segment size (0: automatic, batch_auto_log2_seg of the
+// jobs' symbols), or decode log2 C + kDecThreadsLog2.  decode_split (decode
+// only): 0 every job one lane per chunk, 1 automatic (every job in split
+// units when batch_split_all holds for the jobs' symbols, else the jobs of
+// fewer than kDecThreads chunks), 2 every job in split units.  The plan
+// records the segment size in hdr->log2_seg for the encode kernel.
 hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode,
                              uint32_t decode_split, uint32_t log2_unit, uint64_t max_units,
                              uint32_t lag, BatchHeader* hdr, BatchJobState* js, uint64_t* job_hist,
                              uint32_t* unit_job, uint64_t* seg_word, hipStream_t stream);
 hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t bits, uint32_t mode,
-                                 uint32_t log2_seg, uint32_t log2_chunk, BatchHeader* hdr,
-                                 BatchJobState* js, uint64_t* job_hist, const uint32_t* seg_job,
-                                 uint64_t* seg_word, uint32_t* seg_hist, uint32_t grid,
-                                 hipStream_t stream);
+                                 uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
+                                 uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,
+                                 uint32_t* seg_hist, uint32_t grid, hipStream_t stream);
 hipError_t launch_decode_batched(const qlc_job* jobs, uint32_t bits, uint32_t log2_chunk,
                                  BatchHeader* hdr, const BatchJobState* js,
                                  const uint32_t* grp_job, uint32_t grid, hipStream_t stream);

@@ -2031,6 +2031,23 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
   const uint32_t k0 = tid * per < n_jobs ? tid * per : n_jobs;
   const uint32_t k1 = k0 + per < n_jobs ? k0 + per : n_jobs;
 
+  // ---- symbols of the valid jobs, for the automatic work split ----
+  if ((!decode && log2_unit == 0) || (decode && decode_split == 1)) {
+    uint64_t syms = 0;
+    for (uint32_t k = k0; k < k1; ++k) {
+      const qlc_job jb = jobs[k];
+      if (jb.err && ptr_aligned(jb.err, 4) && job_valid(jb, decode != 0)) syms += jb.n;
+    }
+    const uint64_t incl = wave_inclusive_scan_u64(syms);  // n < 2^36 per job: no overflow
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t T = 0;
+    for (int w = 0; w < kPlanThreads / 64; ++w) T += wsum[w];
+    __syncthreads();
+    if (!decode) log2_unit = batch_auto_log2_seg(T);
+    else if (batch_split_all(T, log2_unit - kDecThreadsLog2)) decode_split = 2;
+  }
+
   // ---- units per job; per-job status reset ----
   uint64_t local = 0;
   uint32_t maxc = 0;
@@ -2098,6 +2115,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
       hdr->units = 0;
       hdr->lag = 0;
       hdr->abort = 1;
+      hdr->log2_seg = log2_unit;
     }
     return;
   }
@@ -2116,6 +2134,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
     hdr->units = (uint32_t)total;
     hdr->lag = (uint32_t)(lag < total ? lag : total);
     hdr->abort = 0;
+    hdr->log2_seg = log2_unit;
   }
 }
 
@@ -2143,7 +2162,7 @@ union BatchEncSmem {
 // At most 128 VGPRs, so that four workgroups share a CU (LDS allows it).
 template <int kBits>
 __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
-    const qlc_job* __restrict__ jobs, uint32_t mode, uint32_t log2_seg, uint32_t log2_chunk,
+    const qlc_job* __restrict__ jobs, uint32_t mode, uint32_t log2_chunk,
     BatchHeader* __restrict__ hdr, BatchJobState* __restrict__ js,
     uint64_t* __restrict__ job_hist, const uint32_t* __restrict__ seg_job,
     uint64_t* __restrict__ seg_word, uint32_t* __restrict__ seg_hist) {
@@ -2152,6 +2171,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
   const uint32_t tid = threadIdx.x;
   const uint32_t G = hdr->units;
   const uint32_t L = hdr->lag;
+  const uint32_t log2_seg = hdr->log2_seg;  // the plan's (given or automatic) segment size
   for (;;) {
     if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
     __syncthreads();
@@ -2391,12 +2411,11 @@ hipError_t launch_batch_plan(const qlc_job* jobs, uint32_t n_jobs, bool decode,
 }
 
 hipError_t launch_encode_batched(const qlc_job* jobs, uint32_t bits, uint32_t mode,
-                                 uint32_t log2_seg, uint32_t log2_chunk, BatchHeader* hdr,
-                                 BatchJobState* js, uint64_t* job_hist, const uint32_t* seg_job,
-                                 uint64_t* seg_word, uint32_t* seg_hist, uint32_t grid,
-                                 hipStream_t stream) {
-  QLC_LAUNCH_BITS(bits, k_encode_batched, dim3(grid), dim3(kEncThreads), jobs, mode, log2_seg,
-                  log2_chunk, hdr, js, job_hist, seg_job, seg_word, seg_hist);
+                                 uint32_t log2_chunk, BatchHeader* hdr, BatchJobState* js,
+                                 uint64_t* job_hist, const uint32_t* seg_job, uint64_t* seg_word,
+                                 uint32_t* seg_hist, uint32_t grid, hipStream_t stream) {
+  QLC_LAUNCH_BITS(bits, k_encode_batched, dim3(grid), dim3(kEncThreads), jobs, mode, log2_chunk,
+                  hdr, js, job_hist, seg_job, seg_word, seg_hist);
   return hipGetLastError();
 }
 

@@ -40,13 +40,23 @@ bool is_aligned(const void* p, uintptr_t a) {
   return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0;
 }
 
-// Per-job (total_bits, err) of a tick into one array, so the host reads
-// every job's status with one copy.
+// Per-job (total_bits, err) of a tick into one array of pinned, mapped host
+// memory, which the host reads once the tick's event has completed (no
+// device-to-host copy).
 __global__ void k_gather_status(const qlc_job* __restrict__ jobs, uint32_t n,
                                 uint64_t* __restrict__ status) {
   for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
     status[2 * j] = *jobs[j].total_bits;
     status[2 * j + 1] = *jobs[j].err;
+  }
+}
+
+// The same for a tick of one request, from its two status words.
+__global__ void k_gather_one(const uint64_t* __restrict__ total, const uint32_t* __restrict__ err,
+                             uint64_t* __restrict__ status) {
+  if (threadIdx.x == 0) {
+    status[0] = *total;
+    status[1] = *err;
   }
 }
 
@@ -111,10 +121,12 @@ struct Slot {
   hipEvent_t done = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  void* plain_ws = nullptr;      // single-tensor workspace (ticks of one request)
+  size_t plain_ws_bytes = 0;
   qlc_job* d_jobs = nullptr;   // compress jobs, then decompress jobs
   qlc_job* h_jobs = nullptr;   // pinned staging of d_jobs
-  uint64_t* d_status = nullptr;
-  uint64_t* h_status = nullptr;  // pinned
+  uint64_t* h_status = nullptr;      // pinned, mapped: (total_bits, err) per job
+  uint64_t* h_status_dev = nullptr;  // its device-side address
   std::vector<Request*> enc, dec;
   bool busy = false;
 };
@@ -221,22 +233,43 @@ struct qlc_server {
     const uint32_t ne = (uint32_t)sl.enc.size(), nd = (uint32_t)sl.dec.size();
     for (uint32_t i = 0; i < ne; ++i) sl.h_jobs[i] = sl.enc[i]->job;
     for (uint32_t i = 0; i < nd; ++i) sl.h_jobs[ne + i] = sl.dec[i]->job;
-    if (hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(qlc_job) * (ne + nd), hipMemcpyHostToDevice,
-                       sl.stream) != hipSuccess)
-      return false;
-    if (ne && qlc_encode_batched(sl.d_jobs, ne, (qlc_layout_mode)cfg.layout_mode,
-                                 cfg.chunk_symbols, &tuning, sl.ws, sl.ws_bytes,
-                                 sl.stream) != QLC_OK)
-      return false;
-    if (nd && qlc_decode_batched(sl.d_jobs + ne, nd, cfg.chunk_symbols, &tuning, sl.ws,
-                                 sl.ws_bytes, sl.stream) != QLC_OK)
-      return false;
-    hipLaunchKernelGGL(k_gather_status, dim3((ne + nd + 255) / 256), dim3(256), 0, sl.stream,
-                       sl.d_jobs, ne + nd, sl.d_status);
+    if (ne + nd == 1) {
+      // A tick of one request runs the single-tensor entry points: for one
+      // job they cost less than the persistent batched launch (no job-array
+      // copy, plan kernel, work queue or cross-workgroup flags), with the
+      // same bytes out.
+      const qlc_job& j = sl.h_jobs[0];
+      qlc_status st;
+      if (ne && j.build_table)
+        st = qlc_compress(j.in, j.n, (qlc_layout_mode)cfg.layout_mode, j.table, cfg.chunk_symbols,
+                          j.bits, j.bits_capacity, j.chunk_index, j.total_bits, j.err,
+                          sl.plain_ws, sl.plain_ws_bytes, sl.stream);
+      else if (ne)
+        st = qlc_encode(j.in, j.n, j.table, cfg.chunk_symbols, j.bits, j.bits_capacity,
+                        j.chunk_index, j.total_bits, j.err, sl.plain_ws, sl.plain_ws_bytes,
+                        sl.stream);
+      else
+        st = qlc_decode_ex(j.bits, j.total_bits, j.chunk_index, cfg.chunk_symbols, j.table, j.n,
+                           8, (qlc_decoder)cfg.decoder, j.out, j.err, sl.plain_ws,
+                           sl.plain_ws_bytes, sl.stream);
+      if (st != QLC_OK) return false;
+      hipLaunchKernelGGL(k_gather_one, dim3(1), dim3(64), 0, sl.stream, j.total_bits, j.err,
+                         sl.h_status_dev);
+    } else {
+      if (hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(qlc_job) * (ne + nd),
+                         hipMemcpyHostToDevice, sl.stream) != hipSuccess)
+        return false;
+      if (ne && qlc_encode_batched(sl.d_jobs, ne, (qlc_layout_mode)cfg.layout_mode,
+                                   cfg.chunk_symbols, &tuning, sl.ws, sl.ws_bytes,
+                                   sl.stream) != QLC_OK)
+        return false;
+      if (nd && qlc_decode_batched(sl.d_jobs + ne, nd, cfg.chunk_symbols, &tuning, sl.ws,
+                                   sl.ws_bytes, sl.stream) != QLC_OK)
+        return false;
+      hipLaunchKernelGGL(k_gather_status, dim3((ne + nd + 255) / 256), dim3(256), 0, sl.stream,
+                         sl.d_jobs, ne + nd, sl.h_status_dev);
+    }
     if (hipGetLastError() != hipSuccess) return false;
-    if (hipMemcpyAsync(sl.h_status, sl.d_status, 16ull * (ne + nd), hipMemcpyDeviceToHost,
-                       sl.stream) != hipSuccess)
-      return false;
     return hipEventRecord(sl.done, sl.stream) == hipSuccess;
   }
 
@@ -310,8 +343,8 @@ struct qlc_server {
   void free_all() {
     for (Slot& sl : slots) {
       if (sl.ws) (void)hipFree(sl.ws);
+      if (sl.plain_ws) (void)hipFree(sl.plain_ws);
       if (sl.d_jobs) (void)hipFree(sl.d_jobs);
-      if (sl.d_status) (void)hipFree(sl.d_status);
       if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
       if (sl.h_status) (void)hipHostFree(sl.h_status);
       if (sl.done) (void)hipEventDestroy(sl.done);
@@ -356,15 +389,19 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
   for (Slot& sl : s->slots) {
     sl.ws_bytes = qlc_batched_workspace_bytes(c.max_jobs_per_tick, c.max_tick_symbols, C,
                                               &s->tuning);
-    ok = ok && sl.ws_bytes &&
+    sl.plain_ws_bytes = qlc_workspace_bytes(c.max_tick_symbols, C);
+    ok = ok && sl.ws_bytes && sl.plain_ws_bytes &&
          hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
          hipMalloc(&sl.ws, sl.ws_bytes) == hipSuccess &&
          hipMalloc((void**)&sl.d_jobs, sizeof(qlc_job) * c.max_jobs_per_tick) == hipSuccess &&
          hipHostMalloc((void**)&sl.h_jobs, sizeof(qlc_job) * c.max_jobs_per_tick) == hipSuccess &&
-         hipMalloc((void**)&sl.d_status, 16ull * c.max_jobs_per_tick) == hipSuccess &&
-         hipHostMalloc((void**)&sl.h_status, 16ull * c.max_jobs_per_tick) == hipSuccess &&
+         hipHostMalloc((void**)&sl.h_status, 16ull * c.max_jobs_per_tick,
+                       hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&sl.h_status_dev, sl.h_status, 0) == hipSuccess &&
          qlc_workspace_init(sl.ws, sl.ws_bytes, sl.stream) == QLC_OK &&
+         hipMalloc(&sl.plain_ws, sl.plain_ws_bytes) == hipSuccess &&
+         qlc_workspace_init(sl.plain_ws, sl.plain_ws_bytes, sl.stream) == QLC_OK &&
          hipStreamSynchronize(sl.stream) == hipSuccess;
     if (!ok) break;
   }

@@ -114,7 +114,7 @@ assert ctypes.sizeof(Job) == JOB_BYTES
 
 
 class BatchTuning(ctypes.Structure):
-    """qlc_batch_tuning: work split of a batched call (0 = default)."""
+    """qlc_batch_tuning: work split of a batched call (0 = automatic)."""
     _fields_ = [
         ("log2_segment", ctypes.c_uint32),
         ("lag_segments", ctypes.c_uint32),

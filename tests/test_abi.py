@@ -135,6 +135,26 @@ def test_batched_workspace_query():
     assert f(1, 1 << 20, 4096, (13, 0, 0, qlc.DECODER_SPLIT)) > 0
 
 
+def test_batched_workspace_query_covers_automatic_segments():
+    """With tuning 0 the segment size is picked on the device from the jobs'
+    total T' (floor(log2 T') / 2 + 4 in 13..19); the workspace sized for at
+    most T symbols must hold the segments of any T' <= T at that size."""
+    f = qlc.qlc_batched_workspace_bytes
+
+    def auto(t):
+        return 13 if t == 0 else min(19, max(13, (t.bit_length() - 1) // 2 + 4))
+    totals = [0, 1, 8191, 65536, 10 ** 6, 1 << 20, 5 * 10 ** 6, 1 << 26, 10 ** 9, 1 << 33, 3 << 35]
+    for n_jobs in (1, 7, 1152):
+        for T in totals:
+            ws = f(n_jobs, T, 2048)
+            assert ws > 0
+            below = sorted({T, T // 2, T // 3, T // 5, T // 17, T // 255, T // 4099, 1, 0} |
+                           {t for t in totals if t <= T} | {(1 << k) - 1 for k in range(1, 40)
+                                                          if (1 << k) - 1 <= T})
+            for t in below:
+                assert ws >= f(n_jobs, t, 2048, (auto(t), 0, 0, 0)), (n_jobs, T, t)
+
+
 def test_batched_argument_errors_are_synchronous():
     L = qlc.lib()
     ws = 1 << 20

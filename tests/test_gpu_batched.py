@@ -405,3 +405,43 @@ def test_autotuner_choice_is_valid_and_output_invariant():
     check_round_trip(b, xs)
     again = autotune.tune_batched(b, 0, chunks=(1024, 2048), log2_segments=(14, 16), lags=(0, 1))
     assert again == ch or again.chunk_symbols in (1024, 2048)
+
+
+def _auto_log2_seg(T):
+    """The documented automatic segment size: floor(log2 T) / 2 + 4 in 13..19."""
+    if T == 0:
+        return 13
+    return min(19, max(13, (T.bit_length() - 1) // 2 + 4))
+
+
+def _split_all(T, C):
+    """The documented automatic decoder choice for a whole batch of T symbols."""
+    lane_fill = 19400 + 44 * C
+    return C <= 16384 and T <= 1 << 40 and 26000 + T * 25 // 10000 < max(lane_fill, T * 46 // 100000)
+
+
+@pytest.mark.parametrize("sizes", [[65536, 77], [1 << 20], [3 << 20, (1 << 20) + 5],
+                                   [9 << 20, 7 << 20, 4099], [20 << 20, 16 << 20, 100003]])
+def test_batched_automatic_work_split(sizes):
+    """Tuning 0 (automatic): the plan picks the documented segment size from
+    the batch's symbols (recorded in the workspace header) and the output
+    matches the oracle; the decode splits the jobs the documented time model
+    and the small-job rule name (recorded per job), and round-trips."""
+    C = 2048
+    b, xs = make_batch(sizes, C)
+    ws = b.workspace()
+    b.encode(ws, qlc.LAYOUT_SEARCH_QUAD)
+    torch.cuda.synchronize()
+    hdr = ws[:32].cpu().numpy().view(np.uint32)
+    T = sum(sizes)
+    assert hdr[4] == _auto_log2_seg(T)
+    assert hdr[1] == sum(max(1, -(-n // (1 << int(hdr[4])))) for n in sizes)   # units
+    check_against_oracle(b, xs, qlc.LAYOUT_SEARCH_QUAD, C)
+    b.out.zero_()
+    b.decode(ws)
+    torch.cuda.synchronize()
+    check_round_trip(b, xs)
+    js = ws[256:256 + 16 * len(sizes)].cpu().numpy().view(np.uint32).reshape(-1, 4)
+    for k, n in enumerate(sizes):
+        want = _split_all(T, C) or -(-n // C) < 256
+        assert js[k, 2] == int(want), (k, n)
