@@ -60,6 +60,27 @@ __global__ void k_gather_one(const uint64_t* __restrict__ total, const uint32_t*
   }
 }
 
+// The largest ws_bytes_for(n) over 0 <= n <= N.  The segment count is not
+// monotone in n (one more symbol can double the segment size), but it is
+// within each stretch of equal seg_log2, so the maximum sits at N or just
+// below a point where seg_log2 steps: n = 2^k (the square-root rule),
+// n = 1025 * 2^l (the ~1024-segment rule) or n = (2^24 + 1) * 2^l (the cap).
+inline size_t ws_bytes_upto(uint64_t N) {
+  size_t m = ws_bytes_for(N);
+  for (uint32_t k = 1; k < 64; ++k) {
+    const uint64_t cands[3] = {
+        (1ull << k) - 1,
+        k <= 53 ? 1025ull * (1ull << k) - 1 : ~0ull,
+        k <= 39 ? ((1ull << 24) + 1) * (1ull << k) - 1 : ~0ull};
+    for (const uint64_t n : cands) {
+      if (n > N) continue;
+      const size_t b = ws_bytes_for(n);
+      if (b > m) m = b;
+    }
+  }
+  return m;
+}
+
 // First-fit allocator over [0, capacity) with coalescing of free blocks.
 class Pool {
  public:
@@ -389,7 +410,7 @@ qlc_status qlc_server_create(const qlc_server_config* h_config, qlc_server** out
   for (Slot& sl : s->slots) {
     sl.ws_bytes = qlc_batched_workspace_bytes(c.max_jobs_per_tick, c.max_tick_symbols, C,
                                               &s->tuning);
-    sl.plain_ws_bytes = qlc_workspace_bytes(c.max_tick_symbols, C);
+    sl.plain_ws_bytes = ws_bytes_upto(c.max_tick_symbols);  // any request size up to it
     ok = ok && sl.ws_bytes && sl.plain_ws_bytes &&
          hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&

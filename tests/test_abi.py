@@ -121,6 +121,15 @@ def test_struct_layouts_match_the_header():
     assert qlc.Job.build_table.offset == 72 and qlc.Job.err.offset == 64
 
 
+def test_workspace_bytes_not_monotone_in_n():
+    """One more symbol can double the segment size and halve the segment
+    count, so a workspace for n symbols need not fit n - 32 (the serving
+    loop sizes its single-tensor workspace for every n up to its limit)."""
+    f = qlc.qlc_workspace_bytes
+    assert f((1 << 22) - 32, 1024) > f(1 << 22, 1024)
+    assert f(1 << 22, 1024) >= f(1 << 21, 1024)
+
+
 def test_batched_workspace_query():
     f = qlc.qlc_batched_workspace_bytes
     a = f(1152, 10 << 30, 2048)

@@ -209,3 +209,28 @@ def test_bad_config():
         qlc.Server(0)
     with pytest.raises(qlc.QLCError):
         qlc.Server(1 << 20, chunk_symbols=1000)
+
+
+def test_single_request_sizes_below_the_tick_limit():
+    """A tick of one request runs the single-tensor entry points on a
+    workspace sized when the server is created; the segment count is not
+    monotone in n (2^22 - 32 symbols take 256 segments, 2^22 take 128), so
+    that workspace must fit every size up to max_tick_symbols, not only the
+    largest.  Each request alone must equal qlc_compress / the original."""
+    limit = 1 << 22
+    sizes = [limit - 32, limit, (1 << 20) - 96, 1025 * 8192 // 4 - 64]
+    with qlc.Server(256 << 20, chunk_symbols=C, max_tick_symbols=limit) as srv:
+        for j, n in enumerate(sizes):
+            x = _bytes(n, 300 + j).to(DEV)
+            ids = _submit_all(srv, [x], [], [("c", 0)])
+            st, total, bits, index, table = _collect(srv, ids)[("c", 0)]
+            ref = qlc.compress(x, chunk_symbols=C)
+            torch.cuda.synchronize()
+            assert st == 0, (n, st)
+            assert total == ref.total_bits(), n
+            assert np.array_equal(bits, ref.bits[:ref.nbytes()].cpu().numpy()), n
+            o = qlc.compress(x, chunk_symbols=C)
+            torch.cuda.synchronize()
+            ids = _submit_all(srv, [], [o], [("d", 0)])
+            st, out = _collect(srv, ids)[("d", 0)]
+            assert st == 0 and np.array_equal(out, x.cpu().numpy()), n
