@@ -2038,7 +2038,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(
       const qlc_job jb = jobs[k];
       if (jb.err && ptr_aligned(jb.err, 4) && job_valid(jb, decode != 0)) syms += jb.n;
     }
-    const uint64_t incl = wave_inclusive_scan_u64(syms);  // n < 2^36 per job: no overflow
+    // n < 2^36 per job, and a workspace (2 KiB of histogram per job) holds
+    // far fewer than 2^28 jobs: the sum stays below 2^64
+    const uint64_t incl = wave_inclusive_scan_u64(syms);
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
     uint64_t T = 0;
