@@ -161,25 +161,29 @@ constexpr uint32_t kPaperT2Packed = 0x85533331u;  // 1,3,3,3,3,5,5,8
 // ---------------------------------------------------------------------------
 // Wave64 helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
-  uint32_t lo = __shfl_up((uint32_t)v, d, 64);
-  uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
+// 64-bit wave operations with DPP (the two halves moved by the same DPP
+// pattern): no LDS round trips, unlike lane shuffles (ds_bpermute).  Lanes
+// with no source lane in a step take `old` (0 for sums, their own value for
+// minima); row_bcast steps write only the rows their mask names.
+#define QLC_DPP_U64(OLD, V, CTRL, ROWS)                                                   \
+  ((uint64_t)(uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(OLD),                  \
+                                                   (int)(uint32_t)(V), CTRL, ROWS, 0xf,     \
+                                                   false) |                                 \
+   ((uint64_t)(uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)((OLD) >> 32),         \
+                                                    (int)(uint32_t)((V) >> 32), CTRL, ROWS, \
+                                                    0xf, false)                             \
+    << 32))
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  uint32_t lo = __shfl_xor((uint32_t)v, m, 64);
-  uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
-
+// Inclusive wave64 scan: Hillis-Steele inside each 16-lane row (row_shr 1,
+// 2, 4, 8), then row 0's total into row 1 and row 2's into row 3
+// (row_bcast:15), then rows 0-1's total into rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ uint64_t wave_inclusive_scan_u64(uint64_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t t = shfl_up_u64(v, d);
-    if (lane >= d) v += t;
-  }
+  v += QLC_DPP_U64(0ull, v, 0x111, 0xf);  // row_shr:1
+  v += QLC_DPP_U64(0ull, v, 0x112, 0xf);  // row_shr:2
+  v += QLC_DPP_U64(0ull, v, 0x114, 0xf);  // row_shr:4
+  v += QLC_DPP_U64(0ull, v, 0x118, 0xf);  // row_shr:8
+  v += QLC_DPP_U64(0ull, v, 0x142, 0xa);  // row_bcast:15
+  v += QLC_DPP_U64(0ull, v, 0x143, 0xc);  // row_bcast:31
   return v;
 }
 
@@ -197,19 +201,34 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan_u32(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_u64(v, m);
-  return v;
+// Lane 63's value, in every lane.
+__device__ __forceinline__ uint64_t lane63_u64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
 }
 
+// Sum over the wave, in every lane (the scan's lane 63).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  return lane63_u64(wave_inclusive_scan_u64(v));
+}
+
+// Minimum over the wave, in every lane (a prefix-minimum scan's lane 63).
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    uint64_t o = shfl_xor_u64(v, m);
-    v = o < v ? o : v;
-  }
-  return v;
+  uint64_t t;
+  t = QLC_DPP_U64(v, v, 0x111, 0xf);
+  v = t < v ? t : v;
+  t = QLC_DPP_U64(v, v, 0x112, 0xf);
+  v = t < v ? t : v;
+  t = QLC_DPP_U64(v, v, 0x114, 0xf);
+  v = t < v ? t : v;
+  t = QLC_DPP_U64(v, v, 0x118, 0xf);
+  v = t < v ? t : v;
+  t = QLC_DPP_U64(v, v, 0x142, 0xa);
+  v = t < v ? t : v;
+  t = QLC_DPP_U64(v, v, 0x143, 0xc);
+  v = t < v ? t : v;
+  return lane63_u64(v);
 }
 
 // ---------------------------------------------------------------------------
