@@ -551,12 +551,13 @@ __global__ __launch_bounds__(kHistThreads) void k_histogram(
 // of its histogram with the code lengths, so every workgroup publishes its
 // count at once and sums its predecessors' counts (all published within a
 // few microseconds: no serial look-back chain).  The workgroup then walks
-// its segment in tiles of 4096 symbols: LUT gather from LDS, block scan of
-// the code lengths, bit packing into LDS at the running global alignment,
-// coalesced stores of the whole words; the partial last word is carried
-// into the next tile.  A segment's first word also holds the last bits of
-// the previous segment, which the workgroup recomputes from the 16 input
-// bytes before its segment; its own partial last word is left to the next
+// its segment in tiles of kEncTile (8192) symbols: LUT gather from LDS,
+// block scan of the code lengths, bit packing into LDS at the running
+// global alignment, coalesced stores of the whole words; the partial last
+// word is carried into the next tile.  A segment's first word also holds
+// the last bits of the previous segment, which the workgroup recomputes
+// from the 32 symbols before its segment (at least 32 bits, since every
+// code has at least one); its own partial last word is left to the next
 // segment (the last segment pads and stores it).
 // ===========================================================================
 struct EncSmem {
