@@ -2175,6 +2175,10 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_encode_batched(
   const uint32_t G = hdr->units;
   const uint32_t L = hdr->lag;
   const uint32_t log2_seg = hdr->log2_seg;  // the plan's (given or automatic) segment size
+  // A workgroup beyond the number of work items takes no ticket: the queue
+  // is drained by the lower-numbered ones, and a small batch does not queue
+  // every resident workgroup's atomic on the one ticket word.
+  if ((uint64_t)blockIdx.x >= 2ull * G) return;
   for (;;) {
     if (tid == 0) s_ticket = atomic_add_u32(&hdr->ticket, 1u);
     __syncthreads();
@@ -2282,6 +2286,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decode_batched(
   __shared__ uint32_t s_ticket;
   const uint32_t tid = threadIdx.x;
   const uint32_t units = hdr->units;
+  if (blockIdx.x >= units) return;  // (as in the encoder: only as many workgroups as items)
   uint32_t cur = ~0u;
   SplitLut L{0, 0, 1, false};
   for (;;) {
