@@ -59,7 +59,7 @@ constexpr uint64_t kValueMask = (1ull << 40) - 1;
 // ---- workspace layout -----------------------------------------------------
 struct WsHeader {
   uint32_t hist_done;   // workgroups finished in the histogram kernel
-  uint32_t enc_ticket;  // next segment handed out by the encode kernel
+  uint32_t reserved0;   // (unused)
   uint32_t enc_done;    // segments finished in the encode kernel
   uint32_t enc_epoch;   // epoch tag of this encode launch's published words
   uint32_t enc_err;     // first data error of the encode launch

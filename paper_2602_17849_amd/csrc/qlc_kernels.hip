@@ -3,6 +3,7 @@
 // Paper: Quad Length Codes for Lossless Compression of e4m3 (arXiv
 // 2602.17849).  Section references are to that paper.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 
 #include "qlc_device.h"
 #include "qlc_kernels.h"
@@ -888,6 +889,16 @@ __global__ __launch_bounds__(kHistThreads) void k_segment_bits(
   }
 }
 
+// Bit count of segment k from its histogram and the code lengths in the
+// encoder LUT (a predecessor's count that was not published in time).
+__device__ __forceinline__ uint64_t segment_bits_from_hist(const uint32_t* __restrict__ h,
+                                                           const uint32_t* lut) {
+  uint64_t b = 0;
+#pragma unroll 8
+  for (int s = 0; s < 256; ++s) b += (uint64_t)h[s] * (lut[s] >> 16);
+  return b;
+}
+
 template <int kBits>
 __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint8_t* __restrict__ in, uint64_t n, uint32_t log2_seg,
@@ -895,11 +906,14 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     const uint64_t* __restrict__ seg_bits, uint32_t log2_chunk, uint32_t* __restrict__ bits_out,
     uint64_t cap_words, uint64_t* __restrict__ index_out, uint64_t* __restrict__ total_out,
     uint32_t* __restrict__ err_out, WsHeader* __restrict__ hdr, uint64_t* __restrict__ seg_word,
-    uint32_t nseg) {
+    uint32_t nseg, uint32_t spin_polls) {
   __shared__ EncSmem S;
   const uint32_t tid = threadIdx.x;
+  // The workgroup's segment is its block index: no shared ticket counter,
+  // whose one atomic per workgroup (all issued at once) cost ~15 us per
+  // launch of 1024 workgroups.
   if (tid == 0) {
-    S.seg = atomic_add_u32(&hdr->enc_ticket, 1u);
+    S.seg = blockIdx.x;
     S.epoch = load_relaxed_u32(&hdr->enc_epoch) & kEpochMask;
     S.cap_hit = 0;
     S.bad_table = 0;
@@ -918,17 +932,28 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
 
   // ---- this segment's bit count, published; the predecessors' summed ----
-  const uint64_t my_bits =
-      seg_bits ? seg_bits[seg]
-               : block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
-  if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
-  uint64_t pre = 0;
-  for (uint32_t k = tid; k < seg; k += kEncThreads) {
-    uint64_t w;
-    do {
-      w = load_relaxed_u64(&seg_word[k]);
-    } while ((w & ~kValueMask) != tag);
-    pre += w & kValueMask;
+  // Given bit counts (a fixed table: k_segment_bits ran before) are summed
+  // directly.  Otherwise each workgroup publishes its count as soon as it
+  // starts and sums its predecessors' published counts; a count still
+  // missing after spin_polls polls (its workgroup not yet running) is
+  // computed here from that segment's histogram, so the wait assumes
+  // nothing about the order or residency of the workgroups.
+  uint64_t my_bits, pre = 0;
+  if (seg_bits) {
+    my_bits = seg_bits[seg];
+    for (uint32_t k = tid; k < seg; k += kEncThreads) pre += seg_bits[k];
+  } else {
+    my_bits = block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
+    if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
+    for (uint32_t k = tid; k < seg; k += kEncThreads) {
+      uint64_t w = load_relaxed_u64(&seg_word[k]);
+      for (uint32_t p = 0; (w & ~kValueMask) != tag && p < spin_polls; ++p) {
+        __builtin_amdgcn_s_sleep(1);
+        w = load_relaxed_u64(&seg_word[k]);
+      }
+      pre += (w & ~kValueMask) == tag ? (w & kValueMask)
+                                      : segment_bits_from_hist(seg_hist + (uint64_t)k * 256, S.lut);
+    }
   }
   const uint64_t G = block_sum_u64(pre, S.red);
   // read after the block sum's barriers, so every thread's length check is in
@@ -963,7 +988,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   if (tid == 0) {
     *err_out = load_relaxed_u32(&hdr->enc_err);
     store_relaxed_u32(&hdr->enc_err, 0);
-    store_relaxed_u32(&hdr->enc_ticket, 0);
     store_relaxed_u32(&hdr->enc_done, 0);
     store_relaxed_u32(&hdr->enc_epoch, (epoch + 1) & kEpochMask);
   }
@@ -2365,6 +2389,18 @@ hipError_t launch_table_from_hist(const uint64_t* hist, uint32_t mode, qlc_table
   return hipGetLastError();
 }
 
+// Polls of a predecessor's published bit count before the encoder computes
+// it itself: QLC_ENCODE_SPIN_POLLS (tests set 0 to take that path for every
+// count not yet published), else 256 (several hundred microseconds, far more
+// than co-resident workgroups take to publish).
+static uint32_t encode_spin_polls() {
+  static const uint32_t polls = [] {
+    const char* e = getenv("QLC_ENCODE_SPIN_POLLS");
+    return e ? (uint32_t)strtoul(e, nullptr, 10) : 256u;
+  }();
+  return polls;
+}
+
 hipError_t launch_encode(const uint8_t* in, uint64_t n, uint32_t bits, const qlc_table* table,
                          const uint32_t* seg_hist, const uint64_t* seg_bits, uint32_t log2_chunk,
                          uint32_t* bits_out, uint64_t cap_words, uint64_t* index_out,
@@ -2373,7 +2409,7 @@ hipError_t launch_encode(const uint8_t* in, uint64_t n, uint32_t bits, const qlc
   const uint32_t nseg = (uint32_t)seg_count(n);
   QLC_LAUNCH_BITS(bits, k_encode, dim3(nseg), dim3(kEncThreads), in, n, seg_log2(n), table,
                   seg_hist, seg_bits, log2_chunk, bits_out, cap_words, index_out, total_out,
-                  err_out, hdr, seg_word, nseg);
+                  err_out, hdr, seg_word, nseg, encode_spin_polls());
   return hipGetLastError();
 }
 

@@ -136,3 +136,41 @@ def test_server_paper_mode_incompressible_bytes(mode):
         assert_table_equal(table, ot)
         assert np.array_equal(index, oindex)
         assert np.array_equal(bits, obits)
+
+
+_FALLBACK_CHILD = r"""
+import sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2602_17849_amd import datagen, qlc
+C = 2048
+for i, n in enumerate([9 * (1 << 20) + 77, (3 << 20) + 5, 262144, 100003]):
+    x = datagen.laplace_outlier_rows(1, (n + 31) // 32 * 32, 40 + i)[:n].contiguous()
+    o = qlc.compress(x.to("cuda"), chunk_symbols=C)
+    torch.cuda.synchronize()
+    xn = x.numpy()
+    ot = oracle.build_table(oracle.histogram(xn), qlc.LAYOUT_SEARCH_QUAD)
+    st, obits, oindex, ototal = oracle.encode(xn, ot, C)
+    assert int(o.err.item()) == 0 and o.total_bits() == ototal, n
+    assert np.array_equal(o.bits[:o.nbytes()].cpu().numpy(), obits), n
+    assert np.array_equal(o.index[:qlc.qlc_chunk_count(n, C)].cpu().numpy().astype(np.uint64),
+                          oindex), n
+print("fallback ok")
+"""
+
+
+def test_encode_predecessor_counts_computed_when_not_yet_published():
+    """With no polls allowed (QLC_ENCODE_SPIN_POLLS=0, read once per
+    process, hence a child process), every predecessor bit count that is not
+    yet published when a workgroup looks is computed by that workgroup from
+    the predecessor's histogram: the streams and indexes still equal the
+    oracle's."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, QLC_ENCODE_SPIN_POLLS="0")
+    r = subprocess.run([sys.executable, "-c", _FALLBACK_CHILD, root], env=env, cwd=root,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0 and "fallback ok" in r.stdout, r.stdout + r.stderr
