@@ -197,7 +197,11 @@ qlc_status qlc_encode(const uint8_t* in, uint64_t n, const qlc_table* table,
 /* Steps 1-5 fused for one tensor: its histogram, a table built from it
  * with `mode` (written to *table_out), then the encoding as qlc_encode.
  * Reads the input twice (histogram, then codes) and never re-reads the
- * table from the host. */
+ * table from the host.  (The encoder's workgroups exchange their segments'
+ * bit counts; one that has waited QLC_ENCODE_SPIN_POLLS polls (an
+ * environment variable read once per process, default 256) for a
+ * predecessor's count computes it itself from that segment's histogram.
+ * The result is the same either way.) */
 qlc_status qlc_compress(const uint8_t* in, uint64_t n, qlc_layout_mode mode,
                         qlc_table* table_out, uint32_t chunk_symbols,
                         uint8_t* bits_out, uint64_t bits_capacity_bytes,
