@@ -566,7 +566,7 @@ struct EncSmem {
   __attribute__((aligned(16))) uint32_t words[2][kEncTile * QLC_MAX_CODE_BITS / 32 + 4];
   uint64_t red[kEncThreads / 64];
   uint32_t wave_sum[kEncThreads / 64];
-  uint32_t seg, epoch, cap_hit, bad_table, is_last;
+  uint32_t epoch, cap_hit, bad_table, is_last;
 };
 
 // Encoder LUT entry of a table's (len << 11) | code word: code | len << 16.
@@ -912,13 +912,15 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   // The workgroup's segment is its block index: no shared ticket counter,
   // whose one atomic per workgroup (all issued at once) cost ~15 us per
   // launch of 1024 workgroups.
+  const uint32_t seg = blockIdx.x;
   if (tid == 0) {
-    S.seg = blockIdx.x;
     S.epoch = load_relaxed_u32(&hdr->enc_epoch) & kEpochMask;
     S.cap_hit = 0;
     S.bad_table = 0;
   }
   const uint32_t e_t = table->enc[tid];
+  // the segment's histogram bin, loaded beside the table entry
+  const uint32_t h_t = seg_bits ? 0u : seg_hist[(uint64_t)seg * 256 + tid];
   S.lut[tid] = enc_entry(e_t);
   for (uint32_t w = tid; w < sizeof(S.words) / 4; w += kEncThreads) (&S.words[0][0])[w] = 0;
   __syncthreads();
@@ -927,7 +929,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
   // the packer in bounds without per-symbol clamps.
   if (!enc_entry_ok<kBits>(e_t, tid) || (tid == 0 && mode_symbol_bits(table->mode) != kBits))
     S.bad_table = 1;
-  const uint32_t seg = S.seg;
   const uint32_t epoch = S.epoch;
   const uint64_t tag = (uint64_t)(0x800000u | epoch) << 40;
 
@@ -943,7 +944,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(
     my_bits = seg_bits[seg];
     for (uint32_t k = tid; k < seg; k += kEncThreads) pre += seg_bits[k];
   } else {
-    my_bits = block_sum_u64((uint64_t)seg_hist[(uint64_t)seg * 256 + tid] * (e_t >> 11), S.red);
+    my_bits = block_sum_u64((uint64_t)h_t * (e_t >> 11), S.red);
     if (tid == 0) store_relaxed_u64(&seg_word[seg], tag | (my_bits & kValueMask));
     for (uint32_t k = tid; k < seg; k += kEncThreads) {
       uint64_t w = load_relaxed_u64(&seg_word[k]);
