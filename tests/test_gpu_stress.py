@@ -80,6 +80,18 @@ def test_stress_4gib(kind):
     assert int(derr.item()) == 0
     assert torch.equal(b.output(0), x), "split decoder round trip"
 
+    if kind == "zeros90":
+        # the single-tensor path on the same buffer: 4096 segments, more
+        # encode workgroups than the device holds at once, so later ones
+        # start as earlier ones finish; the stream equals the batched one
+        o = qlc.compress(x, chunk_symbols=C)
+        torch.cuda.synchronize()
+        assert int(o.err.item()) == 0 and o.total_bits() == total
+        nb = o.nbytes()
+        assert torch.equal(o.bits[:nb], b.bits[b.bits_off[0]:b.bits_off[0] + nb])
+        assert torch.equal(o.index[:(N + C - 1) // C], b.chunk_index(0))
+        del o
+
     if kind == "uniform":
         # Table 1's layout expands incompressible data (8 -> ~9.59 bits)
         del b
