@@ -153,6 +153,7 @@ struct TableSmem {
   uint32_t r2s[256];        // rank -> symbol
   uint32_t width[8], first[8], count[8], offset[8];
   uint64_t cost;
+  uint32_t flagw[16];       // per wave: 1 = a count too large, 2 = a count needing 64-bit keys
   qlc_table stage;          // the table is assembled here, then copied out
 };
 
@@ -179,8 +180,17 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     S.key[s] = (c << 8) | (uint64_t)(255 - s);
     S.key32[s] = (uint32_t)(c << 8) | (uint32_t)(255 - s);
   }
-  big = __syncthreads_or(big);  // (returns whether any thread's value is non-zero)
-  wide = __syncthreads_or(wide);
+  // the two flags over the workgroup: a ballot per wave, one word per wave
+  // in LDS, one barrier
+  {
+    const uint64_t bb = __ballot(big != 0), bw = __ballot(wide != 0);
+    if ((tid & 63) == 0) S.flagw[tid >> 6] = (bb ? 1u : 0u) | (bw ? 2u : 0u);
+    __syncthreads();
+    uint32_t f = 0;
+    for (int w = 0; w < nt / 64; ++w) f |= S.flagw[w];
+    big = (int)(f & 1u);
+    wide = (int)(f >> 1);
+  }
 
   // Rank = number of symbols that sort before s: larger count, or equal
   // count and smaller symbol value, i.e. the number of larger keys (counts
@@ -349,13 +359,9 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
       off = (b == sbits) ? 0u : f;
       term = (uint64_t)(pbits + b) * (S.P[f + cnt] - S.P[f]);
     }
-    // sum of the eight lanes' terms (lanes 8.. repeat lanes 0..7)
-#pragma unroll
-    for (int d = 1; d < 8; d <<= 1) {
-      const uint32_t lo = __shfl_xor((uint32_t)term, d, 64);
-      const uint32_t hi = __shfl_xor((uint32_t)(term >> 32), d, 64);
-      term += ((uint64_t)hi << 32) | lo;
-    }
+    // sum of the eight lanes' terms: the 64 lanes hold each of them eight
+    // times (lane a + 8i repeats lane a)
+    term = wave_sum_u64(term) >> 3;
     if (tid < 8) {
       S.width[a] = w;
       S.first[a] = first;
