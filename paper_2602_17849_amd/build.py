@@ -22,6 +22,8 @@ ARCH = "gfx950"
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-I" + INCLUDE, "-I" + CSRC,
+    # the layout candidate tables are generated at compile time
+    "-fconstexpr-steps=16777216",
     # never emit packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

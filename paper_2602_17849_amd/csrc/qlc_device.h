@@ -25,7 +25,29 @@ struct Candidate {
   uint32_t packed;
   uint32_t lex;
   uint64_t ends;
+  uint64_t steps;  // the width increases (make_steps)
 };
+
+// The width increases of a candidate, for its layout cost in the form
+//   (area-code bits + last width) * N - sum_j d_j * P[e_j]
+// (Abel summation of sum_a w_a * count_a: widths never decrease, P[r] is
+// the count of the ranks below r, e_j the end rank of the area before the
+// j-th increase and d_j its size).  Up to three increases, in bits
+// 13j..13j+12 (e_j: 9 bits, d_j: 4 bits); bit 63 when there are more (the
+// cost is then summed area by area).
+constexpr uint64_t make_steps(const int* w, int na, uint64_t ends) {
+  uint64_t st = 0;
+  int k = 0;
+  for (int a = 0; a + 1 < na; ++a) {
+    const int d = w[a + 1] - w[a];
+    if (d <= 0) continue;
+    if (k == 3) return 1ull << 63;
+    const uint64_t e = (ends >> (8 * a)) & 0xFFu;
+    st |= (e | (uint64_t(d) << 9)) << (13 * k);
+    ++k;
+  }
+  return st;
+}
 
 struct CandidateTable {
   Candidate c[kNumCandidates];
@@ -55,7 +77,8 @@ constexpr CandidateTable make_candidate_table() {
           if (a < 7) ends |= uint64_t(f) << (8 * a);
         }
         if ((d <= 4) == (pass == 0)) {
-          if (n < kNumCandidates) t.c[n] = Candidate{pk, uint32_t(lex) | (uint32_t(d) << 16), ends};
+          if (n < kNumCandidates)
+            t.c[n] = Candidate{pk, uint32_t(lex) | (uint32_t(d) << 16), ends, make_steps(w, 8, ends)};
           ++n;
           if (pass == 0) ++nq;
         }
@@ -99,7 +122,7 @@ constexpr CandidateTable4 make_candidate_table4() {
         f += 1u << w[a];
         if (a < 3) ends |= uint64_t(f) << (8 * a);
       }
-      if (n < kNumCandidates4) t.c[n] = Candidate{pk, uint32_t(n), ends};
+      if (n < kNumCandidates4) t.c[n] = Candidate{pk, uint32_t(n), ends, make_steps(w, 4, ends)};
       ++n;
     }
     int pos = 3;
@@ -141,7 +164,7 @@ constexpr SmallCandidateTable<kMax> make_small_candidates() {
         f += 1u << w[a];
         if (a < kA - 1) ends |= uint64_t(f) << (8 * a);
       }
-      if (n < kMax) t.c[n] = Candidate{pk, uint32_t(n), ends};
+      if (n < kMax) t.c[n] = Candidate{pk, uint32_t(n), ends, make_steps(w, kA, ends)};
       ++n;
     }
     int pos = kA - 1;

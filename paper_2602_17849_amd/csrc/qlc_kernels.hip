@@ -301,15 +301,27 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
       for (int u = 0; u < kCandStep; ++u) {
         const Candidate& cd = cds[u];
         if (i0 + u * nt >= ncand || (cd.lex >> 16) > max_distinct) continue;
-        uint64_t cost = pbits * pN;
-        uint64_t prev = 0;
+        uint64_t cost;
+        if (!(cd.steps >> 63)) {
+          // at most three width increases: three prefix-sum reads
+          const uint32_t wl = (cd.packed >> (4 * (na - 1))) & 15u;
+          cost = (uint64_t)(pbits + wl) * pN;
 #pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          if ((uint32_t)a >= na) break;
-          const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : M;
-          const uint64_t pe = S.P[e];
-          cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
-          prev = pe;
+          for (int j = 0; j < 3; ++j) {
+            const uint32_t sj = (uint32_t)(cd.steps >> (13 * j));
+            cost -= (uint64_t)((sj >> 9) & 15u) * S.P[sj & 0x1FFu];
+          }
+        } else {
+          cost = pbits * pN;
+          uint64_t prev = 0;
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            if ((uint32_t)a >= na) break;
+            const uint32_t e = (uint32_t)a < na - 1 ? (uint32_t)(cd.ends >> (8 * a)) & 0xFFu : M;
+            const uint64_t pe = S.P[e];
+            cost += (uint64_t)((cd.packed >> (4 * a)) & 15u) * (pe - prev);
+            prev = pe;
+          }
         }
         const uint64_t key = (cost << 12) | (uint64_t)(cd.lex & 0xFFFFu);
         if (key < best) {

@@ -18,9 +18,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 def usage():
     if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
         pytest.skip("hipcc not available")
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "--cuda-device-only", "-c",
-           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    from paper_2602_17849_amd import build as qbuild   # the library's own flags
+    cmd = [HIPCC] + [f for f in qbuild.HIPCC_FLAGS if f != "-fPIC"] + [
+           "--cuda-device-only", "-c",
            os.path.join(CSRC, "qlc_kernels.hip"), "-o", os.devnull,
            "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
