@@ -258,9 +258,10 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   } else if (mode == QLC_LAYOUT_PAPER_T2) {
     packed = kPaperT2Packed;
   } else {
-    // cost = 3 * N + sum_a width_a * (ranks' counts in area a); the area
-    // ends come with the candidate, so the eight prefix-sum reads are
-    // independent.
+    // cost = 3 * N + sum_a width_a * (ranks' counts in area a), from the
+    // width increases the candidate carries (make_steps: three prefix-sum
+    // reads) or, for candidates with more, from its area ends (one read per
+    // area); the reads of a candidate are independent.
     const uint32_t max_distinct = mode == QLC_LAYOUT_SEARCH_QUAD ? 4u
                                   : (mode >= 17u && mode <= 24u) ? mode - 16u : 8u;
     const Candidate* ct;
