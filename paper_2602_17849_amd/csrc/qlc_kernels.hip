@@ -144,7 +144,7 @@ static_assert(make_small_candidates<64, 8, kNumCandM64A8>().count == kNumCandM64
 struct TableSmem {
   uint64_t h[256];
   uint64_t key[256];        // count << 8 | (255 - symbol): unique sort keys
-  __attribute__((aligned(16))) uint32_t key32[256];  // the same while counts < 2^24
+  __attribute__((aligned(16))) uint32_t key32[256];  // the same while counts < 2^23
   uint64_t P[257];          // P[r] = sum of the counts of ranks < r
   uint64_t wave_min[16];
   uint32_t wave_pk[16];     // layout of each wave's cheapest candidate
@@ -170,12 +170,12 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
   const uint32_t sbits = mode_symbol_bits(mode);
   const uint32_t M = 1u << sbits;
   int big = 0;   // a count of 2^48 or more, or a count of a symbol outside the alphabet
-  int wide = 0;  // a count of 2^24 or more: the keys need 64 bits
+  int wide = 0;  // a count of 2^23 or more: the keys need 64 bits
   for (int s = tid; s < 256; s += nt) {
     uint64_t c = h_in[s];
     big |= ((c >> 48) != 0 || ((uint32_t)s >= M && c != 0)) ? 1 : 0;
     if ((uint32_t)s >= M) c = 0;
-    wide |= (c >> 24) != 0 ? 1 : 0;
+    wide |= (c >> 23) != 0 ? 1 : 0;
     S.h[s] = c;
     S.key[s] = (c << 8) | (uint64_t)(255 - s);
     S.key32[s] = (uint32_t)(c << 8) | (uint32_t)(255 - s);
@@ -204,14 +204,16 @@ __device__ __forceinline__ void build_table_block(const uint64_t* h_in, uint32_t
     for (int i = tid; i < 256 * parts; i += nt) {
       const int s = i & 255, p = i >> 8;
       uint32_t r = 0;
-      if (!wide) {  // counts below 2^24: 32-bit keys, four per LDS read
+      if (!wide) {  // counts below 2^23: 31-bit keys, four per LDS read
+        // v > ks exactly when ks - v borrows, i.e. sets bit 31 (both keys
+        // below 2^31): no compare-to-mask and its wait states
         const uint32_t ks = S.key32[s];
         const uint4* kk = reinterpret_cast<const uint4*>(&S.key32[p * span]);
 #pragma unroll 8
         for (int u = 0; u < span / 4; ++u) {
           const uint4 v = kk[u];
-          r += (v.x > ks ? 1u : 0u) + (v.y > ks ? 1u : 0u) + (v.z > ks ? 1u : 0u) +
-               (v.w > ks ? 1u : 0u);
+          r += ((ks - v.x) >> 31) + ((ks - v.y) >> 31) + ((ks - v.z) >> 31) +
+               ((ks - v.w) >> 31);
         }
       } else {
         const uint64_t ks = S.key[s];
