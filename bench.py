@@ -379,9 +379,12 @@ def run_calibrated(dev, x, C, reps=10):
     y = torch.empty_like(x)
     derr = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    # the cache-evicting read of the main step, before every encode + decode
+    flush64 = torch.zeros(512 << 20, dtype=torch.uint8, device=dev).view(torch.int64)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
     for k in range(reps + 2):
         e = ev[k - 2] if k >= 2 else None
+        flush64.sum()
         if e:
             e[0].record(stream)
         qlc.qlc_encode(x, table, C, bits, index, total, err, ws)
@@ -617,9 +620,24 @@ def main():
     t_comp = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps / 1e3
     t_dec = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps / 1e3
     ms_per_step = wall / args.steps * 1e3
-    del flush, flush64
 
-    # per-kernel rates: encode with the table fixed, histogram+table alone
+    # per-kernel rates: encode with the table fixed, histogram+table alone;
+    # each call after the same cache-evicting read as a step (mean of reps)
+    def timed_cold(fn, reps=10):
+        fn()
+        evp = []
+        for _ in range(reps):
+            flush64.sum()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            evp.append((e0, e1))
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(b) for a, b in evp) / reps / 1e3
+
+    # ... and back to back (each call also pays for the write-back of the
+    # previous call's output lines)
     def timed(fn, reps=10):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         fn()
@@ -631,7 +649,8 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps / 1e3
 
-    t_enc = timed(lambda: qlc.qlc_encode(x, table, C, bits, index, total, err, ws))
+    t_enc = timed_cold(lambda: qlc.qlc_encode(x, table, C, bits, index, total, err, ws))
+    t_enc_b2b = timed(lambda: qlc.qlc_encode(x, table, C, bits, index, total, err, ws))
     # bits per symbol of the tensor under every layout mode (tables built on
     # the device from its histogram; cost_bits = sum h * len)
     hist = torch.zeros(256, dtype=torch.int64, device=dev)
@@ -646,7 +665,8 @@ def main():
         qlc.qlc_table_from_histogram(hist, mode, lt)
         torch.cuda.synchronize()
         layouts[name] = round(qlc.parse_table(lt)["cost_bits"] / n, 5)
-    t_tab = timed(lambda: qlc.qlc_build_table(x, qlc.LAYOUT_SEARCH_QUAD, table, ws))
+    t_tab = timed_cold(lambda: qlc.qlc_build_table(x, qlc.LAYOUT_SEARCH_QUAD, table, ws))
+    del flush, flush64
     qlc.qlc_compress(x, qlc.LAYOUT_SEARCH_QUAD, table, C, bits, index, total, err, ws)
     torch.cuda.synchronize()
     tb = int(total.item())
@@ -687,10 +707,15 @@ def main():
         "cache": "a 512 MiB device read before every step (outside the event-timed region, "
                  "inside ms_per_step) evicts the input from the 256 MB Infinity Cache and "
                  "leaves it clean; within a step each kernel finds what the kernel before it "
-                 "left there",
+                 "left there; the fixed-table encode, build_table and calibrated_table calls "
+                 "are each timed after the same read (encode_fixed_table_back_to_back_gbps: "
+                 "ten calls in a row, no read between)",
         "compress_gbps": round(n / t_comp / 1e9, 2),
         "decode_gbps": round(n / t_dec / 1e9, 2),
         "encode_fixed_table_gbps": round(n / t_enc / 1e9, 2),
+        "encode_fixed_table_hbm_frac": round(
+            (n + stream_bytes + index_bytes) / t_enc / 1e9 / HBM_PEAK_GBS, 4),
+        "encode_fixed_table_back_to_back_gbps": round(n / t_enc_b2b / 1e9, 2),
         "build_table_gbps": round(n / t_tab / 1e9, 2),
         "bits_per_symbol": round(L, 5),
         "compressibility": round((8 - L) / 8, 5),
