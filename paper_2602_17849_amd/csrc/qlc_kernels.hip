@@ -685,7 +685,7 @@ __device__ __forceinline__ bool encode_tile(EncSeg<kBits>& E, uint64_t t0, EncSm
   const uint32_t lane = tid & 63, wave = tid >> 6;
   bool cap = false;
   uint32_t* const Wd = S.words[E.buf];
-  uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols (whole tiles)
+  uint32_t pc[16], pl[16];  // code pairs of the thread's 32 symbols
   uint32_t b0 = 0, b1 = 0;  // bits of the thread's two runs
   if (kFull) {
     const typename SI::Raw r0 = E.nx0, r1 = E.nx1;
@@ -707,12 +707,24 @@ __device__ __forceinline__ bool encode_tile(EncSeg<kBits>& E, uint64_t t0, EncSm
       else b1 += pl[k];
     }
   } else {
-#pragma unroll 1
+    // The input's ragged last tile: each of the thread's 32 symbols loaded
+    // on its own, all loads issued before the first is used (a symbol past
+    // seg1 reads as 256, whose entry is 0: no code, no length); then the
+    // same code pairs as a whole tile.
+    uint32_t sy[32];
+#pragma unroll
     for (int k = 0; k < 32; ++k) {
       const uint64_t i = t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-      const uint32_t l = i < E.seg1 ? (S.lut[SI::at(E.in, i)] >> 16) : 0u;
-      if (k < 16) b0 += l;
-      else b1 += l;
+      sy[k] = i < E.seg1 ? SI::at(E.in, i) : 256u;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t e0 = sy[2 * k] < 256u ? S.lut[sy[2 * k]] : 0u;
+      const uint32_t e1 = sy[2 * k + 1] < 256u ? S.lut[sy[2 * k + 1]] : 0u;
+      pc[k] = pair_code(e0, e1);
+      pl[k] = pair_len(e0, e1);
+      if (k < 8) b0 += pl[k];
+      else b1 += pl[k];
     }
   }
   const uint32_t packed = b0 | (b1 << 16);
@@ -734,23 +746,10 @@ __device__ __forceinline__ bool encode_tile(EncSeg<kBits>& E, uint64_t t0, EncSm
   {
     Packer P0{0, (g + off0) & 31u, (g + off0) >> 5};
     Packer P1{0, (g + off1) & 31u, (g + off1) >> 5};
-    if (kFull) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) P0.put(Wd, pc[k], pl[k]);
+    for (int k = 0; k < 8; ++k) P0.put(Wd, pc[k], pl[k]);
 #pragma unroll
-      for (int k = 8; k < 16; ++k) P1.put(Wd, pc[k], pl[k]);
-    } else {
-#pragma unroll 1
-      for (int k = 0; k < 32; ++k) {
-        const uint64_t i =
-            t0 + (uint64_t)(k >> 4) * (kEncTile / 2) + (uint64_t)tid * 16 + (k & 15);
-        if (i < E.seg1) {
-          const uint32_t e = S.lut[SI::at(E.in, i)];
-          if (k < 16) P0.put(Wd, e & 0xFFFFu, e >> 16);
-          else P1.put(Wd, e & 0xFFFFu, e >> 16);
-        }
-      }
-    }
+    for (int k = 8; k < 16; ++k) P1.put(Wd, pc[k], pl[k]);
     P0.finish(Wd);
     P1.finish(Wd);
     // chunk index entries: a run's first symbol may start a chunk
