@@ -1191,14 +1191,6 @@ __device__ __forceinline__ void store_group(QLC_GLOBAL uint8_t* p, uint2 v) {
   }
 }
 
-// Decode 8 symbols starting at pm1 + 1; returns them packed little-endian.
-__device__ __forceinline__ uint2 decode_group(DecLane& L, const uint32_t* __restrict__ lut) {
-  const uint32_t q = (uint32_t)L.pm1;
-  uint32_t e[8];
-  L.pm1 += decode_chain(window_read(L.ring, q), q, L.sh_lo, L.sh_hi, lut, e);
-  return pack_group(e, L.errbits);
-}
-
 // Workgroup barrier that orders LDS accesses only: global loads in flight
 // stay in flight across it (__syncthreads() would wait for them).
 __device__ __forceinline__ void lds_barrier() {
@@ -1353,8 +1345,8 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
         (int)(uint32_t)avail, 0x00020000);
 
     // Per-lane state.  Lanes past the last chunk, or whose index entries
-    // are inconsistent, decode nothing but still take part in the wave's
-    // uniform refill / flush schedule.
+    // are inconsistent, load nothing and keep none of what they decode, but
+    // still take part in the wave's uniform refill / flush schedule.
     uint32_t my_groups = 0, rem = 0;
     uint64_t pos0 = 0, end = 0;
     if (j < nchunks) {
@@ -1399,26 +1391,6 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
     QLC_GLOBAL uint8_t* o = out + (((j << log2_chunk) * kBits) >> 3);
     // all lanes of the wave run the same number of groups
     const uint32_t wave_groups = (uint32_t)(C >> 3);
-
-#define QLC_DEC_REFILL(VAL, SBX, PX)                                                    \
-  {                                                                                     \
-    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
-    VAL = ((uint64_t)fsb << kSbLog2Bits) < (L.pm1 + 1 - rel0) + kLookaheadBits;         \
-    SBX = fsb;                                                                          \
-    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
-    fsb += VAL ? 1u : 0u;                                                               \
-  }
-#define QLC_DEC_GROUP(gidx, VAL, SBX, PX)                                               \
-  {                                                                                     \
-    const uint32_t gg = (gidx);                                                         \
-    if (gg < my_groups) stage[stage_slot(gg, tid)] = pack_out<kBits>(decode_group(L, S.lut)); \
-    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
-    VAL = live && gg < my_groups &&                                                     \
-          ((uint64_t)fsb << kSbLog2Bits) < (L.pm1 + 1 - rel0) + kLookaheadBits;         \
-    SBX = fsb;                                                                          \
-    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
-    fsb += VAL ? 1u : 0u;                                                               \
-  }
 
     // Waves whose 64 chunks are all whole and valid (all but at most the
     // last wave) take a branch-free path with four register sets in
@@ -1501,33 +1473,92 @@ __device__ __forceinline__ bool decode_block(const uint8_t* __restrict__ bits, u
       if (vc) ring_put(L.ring, sb0 + sbc, pc_);
       if (vd) ring_put(L.ring, sb0 + sbd, pd_);
     } else {
-      for (uint32_t g = 0; g < wave_groups; g += 8) {
-        QLC_DEC_GROUP(g + 0, va, sba, pa)
-        QLC_DEC_GROUP(g + 1, vb, sbb, pb)
-        QLC_DEC_GROUP(g + 2, va, sba, pa)
-        QLC_DEC_GROUP(g + 3, vb, sbb, pb)
-        QLC_DEC_GROUP(g + 4, va, sba, pa)
-        QLC_DEC_GROUP(g + 5, vb, sbb, pb)
-        QLC_DEC_GROUP(g + 6, va, sba, pa)
-        QLC_DEC_GROUP(g + 7, vb, sbb, pb)
-        __builtin_amdgcn_wave_barrier();
+      // Any other wave (chunks past the end, a short last chunk, an invalid
+      // chunk): the same schedule with two register sets, every lane running
+      // the wave's full count of groups but keeping only its own: its
+      // position stops where its last group ends (later groups decode that
+      // place again), a lane without a chunk loads nothing, and discarded
+      // groups count no errors and are not stored.  The group counts are
+      // wave-uniform: all (lanes in full_lanes), none, or part_groups in
+      // lane part_lane (the short last chunk, the only count in between).
+      constexpr uint32_t R = kStageGroups;
+      constexpr uint32_t kGpl = kBits == 8 ? 1u : 2u;
+      constexpr uint32_t kLpr = R / kGpl;
+      constexpr uint32_t kRuns = 64 / kLpr;
+      const uint32_t part = lane % kLpr;
+      QLC_GLOBAL uint8_t* obase =
+          out + ((((j_wave + lane / kLpr) << log2_chunk) * kBits) >> 3) + part * kGpl * kBits;
+      const uint64_t full_lanes = __ballot(my_groups == wave_groups);
+      const uint64_t pm = __ballot(my_groups != 0 && my_groups != wave_groups);
+      const uint32_t part_lane = pm ? (uint32_t)__builtin_ctzll(pm) : 64u;
+      const uint32_t part_groups =
+          pm ? (uint32_t)__builtin_amdgcn_readlane((int)my_groups, (int)part_lane) : 0u;
+      uint32_t q = (uint32_t)(L.pm1 - rel0);
+      const uint32_t endr = live ? (uint32_t)(end - rel0) : 0u;
+      const uint32_t* ring = L.ring;
+      const uint32_t rs = (uint32_t)base_sb & 3u;
+      Window W = window_read(ring, q + (rs << kSbLog2Bits));
+#define QLC_DEC_UNIT_P(GI, VAL, SBX, PX)                                                \
+  {                                                                                     \
+    uint32_t e[8];                                                                      \
+    const uint32_t adv = decode_chain(W, q, L.sh_lo, L.sh_hi, S.lut, e);                \
+    const bool keep = (GI) < my_groups;                                                 \
+    q += keep ? adv : 0u;                                                               \
+    if (VAL) ring_put(L.ring, sb0 + SBX, PX);                                           \
+    W = window_read(ring, q + (rs << kSbLog2Bits));                                     \
+    VAL = (fsb << kSbLog2Bits) < min(q + 1 + kLookaheadBits, endr);                     \
+    SBX = fsb;                                                                          \
+    PX = load_sb(rsrc, VAL ? (fsb << (kSbLog2Bits - 3)) : kOobOffset);                  \
+    fsb += VAL ? 1u : 0u;                                                               \
+    uint32_t eb = 0;                                                                    \
+    stage[stage_slot((GI), tid)] = pack_out<kBits>(pack_group(e, eb));                  \
+    L.errbits |= keep ? eb : 0u;                                                        \
+  }
+#pragma unroll 1
+      for (uint32_t g0 = 0; g0 < wave_groups; g0 += R) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const uint32_t src = (lane >> 3) + 8u * k;           // lane whose run is stored
-          const uint32_t part = lane & 7u;                      // 8-byte piece of the run
+        for (uint32_t u = 0; u < R; u += 2) {
+          QLC_DEC_UNIT_P(g0 + u + 0, va, sba, pa)
+          QLC_DEC_UNIT_P(g0 + u + 1, vb, sbb, pb)
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (uint32_t k = 0; k < kLpr; ++k) {
+          const uint32_t src = lane / kLpr + kRuns * k;  // lane (chunk) whose run is stored
           const uint32_t stid = (tid & ~63u) | src;
-          const uint2 v = S.stage[stid * kStageGroups + stage_slot(g + part, stid)];
-          const uint64_t jj = grp * kDecThreads + stid;
-          const uint32_t ngrp = (uint32_t)__shfl(my_groups, (int)src, 64);
-          if (g + part < ngrp)
-            store_group<kBits>(
-                out + ((((jj << log2_chunk) + (uint64_t)(g + part) * 8) * kBits) >> 3), v);
+          const uint32_t ngrp = ((full_lanes >> src) & 1u) ? wave_groups
+                                : src == part_lane ? part_groups : 0u;
+          QLC_GLOBAL uint8_t* dst =
+              obase + ((((uint64_t)(kRuns * k) << log2_chunk) * kBits) >> 3) + g0 * kBits;
+          if (kBits == 8) {
+            if (g0 + part < ngrp) gstore_u2(dst, S.stage[stid * R + stage_slot(g0 + part, stid)]);
+          } else {
+            // two groups (8 or 12 bytes at a multiple of 8 or 12), or only
+            // the first when it is the chunk's last whole group
+            const uint32_t ga = g0 + 2 * part;
+            const uint2 a = S.stage[stid * R + stage_slot(ga, stid)];
+            const uint2 b = S.stage[stid * R + stage_slot(ga + 1, stid)];
+            QLC_GLOBAL uint32_t* d32 = (QLC_GLOBAL uint32_t*)dst;
+            if (ga < ngrp) d32[0] = a.x;
+            if (ga + 1 < ngrp) {
+              if (kBits == 4) {
+                d32[1] = b.x;
+              } else {
+                d32[1] = (a.y & 0xFFFFu) | (b.x << 16);
+                d32[2] = (b.x >> 16) | (b.y << 16);
+              }
+            } else if (kBits == 6 && ga < ngrp) {
+              *(QLC_GLOBAL uint16_t*)(dst + 4) = (uint16_t)a.y;
+            }
+          }
         }
         __builtin_amdgcn_wave_barrier();
       }
+#undef QLC_DEC_UNIT_P
+      // a lane that decoded no group keeps its 64-bit position (q holds it
+      // modulo 2^32, which for the stream's first bit, pm1 = -1, is not it)
+      if (my_groups) L.pm1 = rel0 + q;
     }
-#undef QLC_DEC_REFILL
-#undef QLC_DEC_GROUP
     if (va) ring_put(L.ring, sb0 + sba, pa);
     if (vb) ring_put(L.ring, sb0 + sbb, pb);
     if (live && rem) {  // final partial group of the last chunk
