@@ -1677,7 +1677,7 @@ constexpr uint32_t kSplitSpanWords = kSplitPadWords + kSplitLoadWords;
 constexpr uint32_t kSplitLoadsPerLane = (kSplitLoadWords / 4 + kSplitThreads - 1) / kSplitThreads;
 constexpr uint32_t kSplitQOff = kSplitPadWords * 32 - 1;      // LDS bit of stream bit 0, minus one
 constexpr uint32_t kSplitMaxChunks = kSplitSyms >> 8;         // chunks per workgroup at C = 256
-constexpr uint32_t kSplitWarmBits = 384;                      // walked before a piece, not counted
+constexpr uint32_t kSplitWarmBits = 512;                      // walked before a piece, not counted
 
 struct SplitSmem {
   uint32_t lut[2048];
