@@ -116,7 +116,7 @@ def _check(x, t, C, warm_bits):
 
 
 @pytest.mark.parametrize("C", [256, 2048])
-@pytest.mark.parametrize("warm_bits", [0, 384])
+@pytest.mark.parametrize("warm_bits", [0, 512])
 def test_model_on_skewed_and_uniform_data(C, warm_bits):
     rng = np.random.default_rng(C + warm_bits)
     x = np.clip(np.round(rng.laplace(128, 6, 12289)), 0, 255).astype(np.uint8)
@@ -135,7 +135,7 @@ def test_model_never_meeting_starts_take_g_rounds():
     t = oracle.build_table(oracle.histogram(x), 0)
     G = C // 64
     assert G - 1 <= _check(x, t, C, 0) <= G + 1     # one more exact lane per round
-    assert _check(x, t, C, 384) <= G + 1
+    assert _check(x, t, C, 512) <= G + 1
 
 
 def test_model_small_alphabet_tables():
@@ -143,4 +143,4 @@ def test_model_small_alphabet_tables():
     for M, A, p in ((16, 2, 1), (16, 4, 2), (64, 8, 3)):
         x = np.minimum(rng.geometric(0.3, 7001) - 1, M - 1).astype(np.uint8)
         t = oracle.build_table_general(oracle.histogram(x)[:M], M, A, p, A)
-        _check(x, t, 512, 384)
+        _check(x, t, 512, 512)
