@@ -261,7 +261,7 @@ qlc_status qlc_decode(const uint8_t* bits, const uint64_t* total_bits,
  *                      with the shorter estimated time, from models of both
  *                      fitted on MI355X (256 MiB down to 1 Mi symbols):
  *                      LANE  max(14.6 us + 36.7 ns * C, 0.615 ps * n),
- *                      SPLIT 25 us + 1.28 ps * n (only for C <= 16384).
+ *                      SPLIT 21.3 us + 1.235 ps * n (only for C <= 16384).
  * symbol_bits as in the *_sym entry points below (8 for bytes); other
  * arguments and errors as qlc_decode. */
 typedef enum qlc_decoder {

@@ -366,13 +366,14 @@ qlc_status qlc_compress_noalloc(const uint8_t* in, uint64_t n, qlc_layout_mode m
 // fitted to measured decode times on MI355X: one lane per chunk walks C
 // codes in sequence (a fixed cost plus 36.7 ns per code) unless the chunks
 // fill the device, where it takes 0.615 ps per symbol (1.63 TB/s); the
-// split decoder costs 25 us plus 1.28 ps per symbol.
+// split decoder costs 21.3 us plus 1.235 ps per symbol (1 to 128 Mi
+// symbols, 512-bit warm-up).
 static qlc_decoder auto_decoder(uint64_t n, uint32_t log2c) {
   if (log2c > kSplitMaxLog2Chunk) return QLC_DECODER_LANE;
   const uint64_t C = 1ull << log2c;
   const uint64_t lane_walk = 14600 + C * 367 / 10, lane_rate = n * 615 / 1000000;
   const uint64_t lane = lane_walk > lane_rate ? lane_walk : lane_rate;
-  const uint64_t split = 25000 + n * 128 / 100000;
+  const uint64_t split = 21300 + n * 1235 / 1000000;
   return split < lane ? QLC_DECODER_SPLIT : QLC_DECODER_LANE;
 }
 

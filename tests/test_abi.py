@@ -256,11 +256,14 @@ def test_host_table_deserialize_small_alphabets(M, A, p):
 
 def test_decoder_choice():
     """QLC_DECODER_AUTO's rule: the shorter of two fitted time models (lane:
-    max(14.6 us + 36.7 ns * C, 0.615 ps * n); split: 25 us + 1.28 ps * n,
-    C <= 16384), checked at the measured points it was fitted to."""
+    max(14.6 us + 36.7 ns * C, 0.615 ps * n); split: 21.3 us + 1.235 ps * n,
+    C <= 16384), checked at measured points (split decode with a 512-bit
+    warm-up, Laplace e4m3, sizes with a ragged end)."""
     ch = qlc.qlc_decoder_choice
     L, S = qlc.DECODER_LANE, qlc.DECODER_SPLIT
-    assert ch(1 << 20, 256) == L and ch(1 << 22, 256) == L        # short chunks: lanes suffice
+    assert ch(1 << 20, 256) == S                                   # 22.3 vs 23.8 us
+    assert ch(1 << 22, 256) == L                                   # short chunks: lanes suffice
+    assert ch(8400928, 512) == S and ch(16789536, 512) == L        # 30.3 / 34.3, 41.5 / 34.5 us
     assert ch(1 << 20, 2048) == S and ch(9437184, 2048) == S and ch(1 << 24, 2048) == S
     assert ch(1 << 26, 2048) == L and ch(1 << 28, 2048) == L      # enough chunks to fill
     assert ch(1 << 26, 4096) == S and ch(1 << 28, 4096) == L
